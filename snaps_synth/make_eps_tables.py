@@ -1,0 +1,70 @@
+"""Write the stored per-space epsilon tables of the synthetic workloads.
+
+Each epsilon is chosen by the CPU oracle's sampled-distance rule
+(``oracle.eps_sampled_mean_count``: m seeded sample objects, their float64
+distances to every other object, the radius at which the sample's mean
+neighbour count reaches the target), rounded to float32, and stored so that
+the oracle and the GPU library receive the identical value.  This script
+calls only the oracle and the generators.
+
+    python -m snaps_synth.make_eps_tables c1      # 32,752 spaces, target 10
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+from multiprocessing import Pool
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle as O                      # noqa: E402
+from snaps_synth import generators as G  # noqa: E402
+
+C1_SAMPLES = 128
+C1_TARGET = 10
+
+_X = None
+
+
+def _init(x):
+    global _X
+    _X = x
+
+
+def _c1_one(args):
+    idx, mask = args
+    xs = O.project(_X, int(mask))
+    return idx, O.eps_sampled_mean_count(xs, C1_TARGET, C1_SAMPLES, seed=int(mask))
+
+
+def c1(workers: int) -> str:
+    x, masks, _ = G.gen_c1()
+    eps = np.zeros(len(masks), dtype=np.float32)
+    t0 = time.time()
+    with Pool(workers, initializer=_init, initargs=(x,)) as pool:
+        for i, (idx, e) in enumerate(pool.imap_unordered(_c1_one, list(enumerate(masks)), chunksize=64)):
+            eps[idx] = e
+            if i % 2048 == 0:
+                print(f"{i}/{len(masks)} spaces, {time.time() - t0:.0f} s", flush=True)
+    os.makedirs(G.TABLE_DIR, exist_ok=True)
+    out = os.path.join(G.TABLE_DIR, "c1_eps.npz")
+    np.savez(out, masks=masks, eps=eps, samples=np.int64(C1_SAMPLES), target=np.int64(C1_TARGET))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["c1"])
+    ap.add_argument("--workers", type=int, default=os.cpu_count() or 4)
+    a = ap.parse_args()
+    print(c1(a.workers))
+
+
+if __name__ == "__main__":
+    main()
