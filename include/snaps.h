@@ -1,0 +1,179 @@
+/*
+ * snaps.h -- C ABI of the MI355X similarity self-join library (libsnaps.so).
+ *
+ * The library computes, for one population of objects and one feature
+ * subspace at a time (or for thousands of such jobs in one call), the two
+ * similarity self-joins of the SNAPS population outlier detector and their
+ * four per-object outlier metrics and rankings:
+ *
+ *   - the eps-range self-join ("distance similarity self-join", paper
+ *     Sec. 3.5): every other object within Euclidean distance eps.  Metrics:
+ *     the neighbour count (Sec. 3.5.1, distance-oblivious; fewest = most
+ *     outlying) and the mean neighbour distance (distance-aware; largest =
+ *     most outlying; 0 and most outlying when there is no neighbour,
+ *     Sec. 3.7 / Tab. 2 point 10);
+ *   - the k-nearest-neighbour self-join (Sec. 3.6): the k nearest other
+ *     objects of every object (Fig. 1b).  Metrics: the in-degree of the kNN
+ *     graph (Sec. 3.6.1, distance-oblivious; fewest = most outlying) and the
+ *     mean distance to the k neighbours (distance-aware; largest = most
+ *     outlying);
+ *   - dense 0-based rankings of the four metrics, rank 0 = most outlying,
+ *     equal values sharing a rank (Sec. 3.4, Tab. 2).
+ *
+ * Conventions shared by every entry point
+ *   Memory:   every array argument is DEVICE memory owned by the caller
+ *             (allocate it with hipMalloc or a framework allocator).  The
+ *             library allocates no device memory of its own: scratch space
+ *             comes from the caller's workspace (`ws`, `ws_bytes`), sized with
+ *             the matching *_workspace_bytes query.  Structs passed by
+ *             pointer (populations, jobs, tuning) live in HOST memory and are
+ *             read during the call only.
+ *   Layout:   a population is feature-major: value of feature f of object i
+ *             at cols[f * ld + i], ld >= n.  Features are min-max normalised
+ *             to [0, 1] and finite (Sec. 3.3); the library does not check.
+ *   Spaces:   a subspace is a bit mask over the population's features (bit f
+ *             = feature f); it needs 2..16 set bits, all < n_features.
+ *   Ids:      objects are identified by their row index i (int32, n < 2^31).
+ *   Ties:     the k-th neighbour is chosen in ascending (distance, id) order,
+ *             so equal distances go to the lower id; the eps ball is closed
+ *             (distance <= eps).  Objects never count as their own neighbour.
+ *   Streams:  `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *             asynchronous on it; argument errors are reported by the return
+ *             code immediately, device faults surface at the next call or
+ *             synchronisation as SNAPS_EDEVICE.
+ *   Errors:   functions return a snaps_status; snaps_last_error() gives a
+ *             message for the last non-OK return of the calling thread.
+ *   Numerics: distances are evaluated in float32 in the direct form
+ *             sum_f (x_f - y_f)^2; eps sums are accumulated in float64.
+ *   Limits:   n <= 32768 objects per job in this version (larger n returns
+ *             SNAPS_EUNSUPPORTED); 1 <= k <= min(32, n - 1).
+ */
+#ifndef SNAPS_H
+#define SNAPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SNAPS_OK = 0,
+    SNAPS_EINVAL = -1,       /* invalid argument (message via snaps_last_error) */
+    SNAPS_ENOMEM = -2,       /* workspace too small */
+    SNAPS_EDEVICE = -3,      /* HIP runtime or device error */
+    SNAPS_EUNSUPPORTED = -4  /* valid request outside this version's limits */
+} snaps_status;
+
+/* A population: n objects with n_features normalised features (device). */
+typedef struct {
+    const float* cols;      /* [n_features][ld] device array */
+    int64_t ld;             /* leading dimension, >= n */
+    int64_t n;              /* number of objects, >= 2 */
+    int32_t n_features;     /* 2..32 */
+} snaps_population;
+
+/* Per-object metric outputs of one job (device arrays of length n, indexed
+ * by object id). */
+typedef struct {
+    int32_t* eps_count;     /* neighbours within eps (Sec. 3.5.1 distance-oblivious) */
+    float* eps_mean;        /* their mean distance, 0 if none (Sec. 3.5.1 distance-aware) */
+    int32_t* indeg;         /* kNN-graph in-degree (Sec. 3.6.1 distance-oblivious) */
+    float* knn_mean;        /* mean distance to the k neighbours (Sec. 3.6.1 distance-aware) */
+} snaps_scores;
+
+/* One (population, subspace) job. */
+typedef struct {
+    const snaps_population* pop;
+    uint32_t mask;          /* subspace */
+    int32_t k;              /* neighbours per object */
+    float eps;              /* range radius, > 0 and finite */
+    snaps_scores out;       /* required */
+    int32_t* rank;          /* [4][n] device or NULL: dense ranks of (eps_count, eps_mean,
+                               indeg, knn_mean), 0 = most outlying */
+} snaps_job;
+
+/* Optional tuning (NULL or zero fields = automatic). */
+typedef struct {
+    int32_t mode;           /* 0 auto, 1 brute force over every candidate tile,
+                               2 skip candidate tiles whose bounding box is provably out of reach */
+    int32_t split;          /* 0 auto, else waves sharing one query tile: 1, 2, 4 or 8 */
+    int32_t index_dims;     /* 0 auto (min(d, 6), as Sec. 3.8.1), else 1..min(d, 6) */
+    int32_t filter;         /* 0 auto, 1 direct distance form only,
+                               2 expanded-form prefilter with exact direct recheck */
+    int32_t reserved[4];    /* must be 0 */
+} snaps_tuning;
+
+/* Operation codes of snaps_workspace_bytes. */
+#define SNAPS_OP_KNN 0
+#define SNAPS_OP_EPS 1
+#define SNAPS_OP_SCORES 2
+#define SNAPS_OP_RANK 3
+
+/* Message of the last non-OK return on this thread ("" if none).  The
+ * pointer stays valid until the next library call on the same thread. */
+const char* snaps_last_error(void);
+
+/* Library version string. */
+const char* snaps_version(void);
+
+/* Workspace bytes needed by one call of the given operation on one job of n
+ * objects in a d-dimensional subspace with k neighbours (k is ignored by
+ * SNAPS_OP_EPS and SNAPS_OP_RANK, d by SNAPS_OP_RANK).  Returns 0 for
+ * invalid arguments.  Pure host function. */
+size_t snaps_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t k);
+
+/* Workspace bytes needed by snaps_outlier_scores for this list of jobs.
+ * Returns 0 for invalid arguments.  Pure host function. */
+size_t snaps_outlier_scores_workspace(const snaps_job* jobs, int32_t n_jobs,
+                                      const snaps_tuning* tune);
+
+/* kNN self-join (Sec. 3.6, Fig. 1b): for every object i of population P in
+ * subspace `mask`, its k nearest other objects in ascending (distance, id)
+ * order.
+ *   ids   [n][k] int32 device, output: neighbour ids, row i = object i
+ *   dist  [n][k] float device, output: their Euclidean distances (or NULL)
+ * Returns SNAPS_EINVAL for k < 1, k > n-1, a bad mask or population. */
+int snaps_knn_selfjoin(const snaps_population* P, uint32_t mask, int32_t k,
+                       int32_t* ids, float* dist,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* eps-range self-join (Sec. 3.5): for every object, the number of other
+ * objects at Euclidean distance <= eps and their mean distance.
+ *   count      [n] int32 device, output
+ *   mean_dist  [n] float device, output (0 where count is 0), or NULL
+ *   pair_off, pairs, pair_cap: the pair list is not produced by this
+ *   version; pass NULL, NULL, 0 (anything else returns SNAPS_EUNSUPPORTED).
+ * Returns SNAPS_EINVAL for eps <= 0 or non-finite, a bad mask or population. */
+int snaps_eps_selfjoin(const snaps_population* P, uint32_t mask, float eps,
+                       int32_t* count, float* mean_dist,
+                       int64_t* pair_off, int32_t* pairs, int64_t pair_cap,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Both joins, the four metrics (Sec. 3.5.1, 3.6.1) and, where job.rank is
+ * not NULL, the four dense rankings (Sec. 3.4) for n_jobs independent jobs
+ * in one call.  Jobs may share populations; their outputs must not overlap.
+ * With n_jobs > 1 the job table is uploaded to the workspace by a copy from
+ * host memory, which may wait for earlier work on `stream`.
+ * Returns SNAPS_EINVAL for any invalid job (nothing is launched),
+ * SNAPS_ENOMEM if ws_bytes < snaps_outlier_scores_workspace(...). */
+int snaps_outlier_scores(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Dense rankings of the four metrics of one job (Sec. 3.4, Tab. 2): rank 0
+ * is the most outlying; eps_count and indeg rank ascending, eps_mean and
+ * knn_mean descending, and objects with eps_count == 0 rank first on
+ * eps_mean whatever their stored mean.
+ *   rank  [4][n] int32 device, output, rows in the order
+ *         (eps_count, eps_mean, indeg, knn_mean)
+ * eps_count and indeg values must lie in [0, n). */
+int snaps_rank(const int32_t* eps_count, const float* eps_mean, const int32_t* indeg,
+               const float* knn_mean, int64_t n, int32_t* rank,
+               void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNAPS_H */

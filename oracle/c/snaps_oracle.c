@@ -44,11 +44,15 @@ int oracle_num_threads(void) {
  * next     float64 [m]    (k+1)-th distance, +inf if none
  * cnt      int32 [m]      number of neighbours with D <= eps
  * sum      float64 [m]    sum of those distances
+ * band     int32 [m]      number of other objects with band_lo <= D <= band_hi
+ *                         (NULL to skip); tests use it to find objects that
+ *                         have a neighbour within rounding distance of eps
  * k may be 0 (no kNN), eps may be negative (no range join).
  */
 int oracle_join(const float* x, int64_t n, int32_t d, const float* q, int64_t m,
                 int32_t k, double eps, int32_t* ids, double* dist, double* next,
-                int32_t* cnt, double* sum, int32_t nthreads) {
+                int32_t* cnt, double* sum, int32_t* band, double band_lo, double band_hi,
+                int32_t nthreads) {
     if (n < 1 || d < 1 || k < 0 || k > 64) return -1;
     const int self = (q == 0);
     if (self) { q = x; m = n; }
@@ -65,7 +69,7 @@ int oracle_join(const float* x, int64_t n, int32_t d, const float* q, int64_t m,
         int64_t bj[65];
         int kk = k + 1;              /* keep one extra to report the next distance */
         for (int t = 0; t < kk; ++t) { bd[t] = INFINITY; bj[t] = INT64_MAX; }
-        int32_t c = 0;
+        int32_t c = 0, bc = 0;
         double s = 0.0;
         const float* qi = q + i * (int64_t)d;
         for (int64_t j = 0; j < n; ++j) {
@@ -78,6 +82,7 @@ int oracle_join(const float* x, int64_t n, int32_t d, const float* q, int64_t m,
             }
             double dj = sqrt(acc);
             if (dj <= eps) { c += 1; s += dj; }
+            if (dj >= band_lo && dj <= band_hi) bc += 1;
             if (kk > 1 && before(dj, j, bd[kk - 1], bj[kk - 1])) {
                 int p = kk - 1;
                 while (p > 0 && before(dj, j, bd[p - 1], bj[p - 1])) {
@@ -96,6 +101,7 @@ int oracle_join(const float* x, int64_t n, int32_t d, const float* q, int64_t m,
         if (next) next[i] = (k > 0) ? bd[k] : INFINITY;
         if (cnt) cnt[i] = c;
         if (sum) sum[i] = s;
+        if (band) band[i] = bc;
     }
     return 0;
 }

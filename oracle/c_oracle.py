@@ -41,7 +41,8 @@ def _load():
         lib.oracle_join.argtypes = [
             ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
             ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+            ctypes.c_int32]
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -51,9 +52,11 @@ def num_threads() -> int:
     return int(_load().oracle_num_threads())
 
 
-def join(X, k: int, eps: float, queries=None, nthreads: int = 0):
+def join(X, k: int, eps: float, queries=None, nthreads: int = 0, band=None):
     """Raw join results for a projected population ``X`` [n, d] (float32
-    values).  Returns dict(knn_ids, knn_dist, knn_next, eps_count, eps_sum)."""
+    values).  Returns dict(knn_ids, knn_dist, knn_next, eps_count, eps_sum)
+    and, when ``band=(lo, hi)`` is given, ``band``: the number of other
+    objects at a distance in [lo, hi]."""
     lib = _load()
     x = np.ascontiguousarray(X, dtype=np.float32)
     n, d = x.shape
@@ -70,24 +73,33 @@ def join(X, k: int, eps: float, queries=None, nthreads: int = 0):
     nxt = np.zeros(m, dtype=np.float64)
     cnt = np.zeros(m, dtype=np.int32)
     ssum = np.zeros(m, dtype=np.float64)
+    bnd = np.zeros(m, dtype=np.int32)
+    blo, bhi = (band if band is not None else (1.0, -1.0))
     rc = lib.oracle_join(x.ctypes.data, n, d, qp, m, k, float(eps), ids.ctypes.data,
                          dist.ctypes.data, nxt.ctypes.data, cnt.ctypes.data, ssum.ctypes.data,
+                         bnd.ctypes.data if band is not None else None, float(blo), float(bhi),
                          int(nthreads))
     if rc != 0:
         raise ValueError("oracle_join rejected its arguments")
-    return dict(knn_ids=ids[:, :k].astype(np.int64), knn_dist=dist[:, :k], knn_next=nxt,
-                eps_count=cnt.astype(np.int64), eps_sum=ssum)
+    out = dict(knn_ids=ids[:, :k].astype(np.int64), knn_dist=dist[:, :k], knn_next=nxt,
+               eps_count=cnt.astype(np.int64), eps_sum=ssum)
+    if band is not None:
+        out["band"] = bnd.astype(np.int64)
+    return out
 
 
-def outlier_scores(X, k: int, eps: float, nthreads: int = 0) -> dict:
+def outlier_scores(X, k: int, eps: float, nthreads: int = 0, band=None) -> dict:
     """Same result as :func:`oracle.snaps_oracle.outlier_scores`, with the
-    O(n^2) scan done by the C twin."""
-    r = join(X, k, eps, nthreads=nthreads)
+    O(n^2) scan done by the C twin (plus ``band`` counts when asked)."""
+    r = join(X, k, eps, nthreads=nthreads, band=band)
     n = r["eps_count"].shape[0]
     cnt = r["eps_count"]
     mean = np.where(cnt > 0, r["eps_sum"] / np.maximum(cnt, 1), 0.0)
     deg = O.indegree(r["knn_ids"], n)
     kmean = r["knn_dist"].sum(axis=1) / k
     ranks = O.rank_metrics(cnt, mean, deg, kmean)
-    return dict(knn_ids=r["knn_ids"], knn_dist=r["knn_dist"], knn_next=r["knn_next"],
-                eps_count=cnt, eps_mean=mean, indeg=deg, knn_mean=kmean, rank=ranks)
+    out = dict(knn_ids=r["knn_ids"], knn_dist=r["knn_dist"], knn_next=r["knn_next"],
+               eps_count=cnt, eps_mean=mean, indeg=deg, knn_mean=kmean, rank=ranks)
+    if band is not None:
+        out["band"] = r["band"]
+    return out

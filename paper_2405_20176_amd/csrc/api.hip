@@ -1,0 +1,511 @@
+// C ABI of libsnaps: argument validation, workspace layout, job tables and
+// the launch sequence of the similarity self-join passes.
+#include "snaps_internal.h"
+#include "../../include/snaps.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace snaps {
+hipError_t launch_rank_single(const DevJob& j, hipStream_t s);
+}
+
+using namespace snaps;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(SNAPS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int popcount32(uint32_t m) { return __builtin_popcount(m); }
+
+int ceil_log2(int64_t v) {
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+int check_population(const snaps_population* P, uint32_t mask) {
+    if (!P) return fail(SNAPS_EINVAL, "population is NULL");
+    if (!P->cols) return fail(SNAPS_EINVAL, "population columns are NULL");
+    if (P->n < 2) return fail(SNAPS_EINVAL, "population needs n >= 2 objects (n = %lld)", (long long)P->n);
+    if (P->ld < P->n) return fail(SNAPS_EINVAL, "leading dimension %lld < n %lld", (long long)P->ld, (long long)P->n);
+    if (P->n_features < 2 || P->n_features > 32)
+        return fail(SNAPS_EINVAL, "n_features must be in [2, 32] (got %d)", P->n_features);
+    if (P->n_features < 32 && (mask >> P->n_features) != 0)
+        return fail(SNAPS_EINVAL, "mask 0x%x names features beyond n_features = %d", mask, P->n_features);
+    const int d = popcount32(mask);
+    if (d < 2 || d > kMaxD) return fail(SNAPS_EINVAL, "subspace needs 2..%d features (mask 0x%x has %d)", kMaxD, mask, d);
+    if (P->n > kLdsSortMax)
+        return fail(SNAPS_EUNSUPPORTED, "n = %lld objects exceeds this version's limit of %d per job",
+                    (long long)P->n, kLdsSortMax);
+    return SNAPS_OK;
+}
+
+int check_k(int64_t n, int32_t k) {
+    if (k < 1 || k > n - 1) return fail(SNAPS_EINVAL, "k must be in [1, n-1] (k = %d, n = %lld)", k, (long long)n);
+    if (k > kMaxK) return fail(SNAPS_EUNSUPPORTED, "k = %d exceeds this version's limit of %d", k, kMaxK);
+    return SNAPS_OK;
+}
+
+int check_eps(float eps) {
+    if (!(eps > 0.f) || !std::isfinite(eps)) return fail(SNAPS_EINVAL, "eps must be positive and finite");
+    return SNAPS_OK;
+}
+
+int check_tuning(const snaps_tuning* t) {
+    if (!t) return SNAPS_OK;
+    if (t->mode < 0 || t->mode > 2) return fail(SNAPS_EINVAL, "tuning.mode must be 0, 1 or 2");
+    if (!(t->split == 0 || t->split == 1 || t->split == 2 || t->split == 4 || t->split == 8))
+        return fail(SNAPS_EINVAL, "tuning.split must be 0, 1, 2, 4 or 8");
+    if (t->index_dims < 0 || t->index_dims > kMaxIndexDims) return fail(SNAPS_EINVAL, "tuning.index_dims must be in [0, 6]");
+    if (t->filter < 0 || t->filter > 2) return fail(SNAPS_EINVAL, "tuning.filter must be 0, 1 or 2");
+    for (int i = 0; i < 4; ++i)
+        if (t->reserved[i] != 0) return fail(SNAPS_EINVAL, "tuning.reserved must be zero");
+    return SNAPS_OK;
+}
+
+// Device properties, cached per device.
+struct DeviceInfo {
+    int cus = 0;
+};
+
+std::mutex g_dev_mu;
+std::map<int, DeviceInfo> g_dev;
+
+int device_info(DeviceInfo* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev.find(dev);
+    if (it == g_dev.end()) {
+        DeviceInfo di;
+        e = hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+        it = g_dev.emplace(dev, di).first;
+    }
+    *out = it->second;
+    return SNAPS_OK;
+}
+
+// What one job needs, decided on the host.
+struct JobPlan {
+    int32_t n, d, k, kc, ntiles;
+    size_t xs_off, perm_off, box_off, bytes;
+};
+
+JobPlan plan_job(int64_t n, int d, int k) {
+    JobPlan p{};
+    p.n = (int32_t)n;
+    p.d = d;
+    p.k = k;
+    p.kc = kc_class(k);
+    p.ntiles = (int32_t)((n + kTile - 1) / kTile);
+    const size_t rows = (size_t)p.ntiles * kTile;
+    const int dp = row_stride(d);
+    size_t off = 0;
+    p.xs_off = off;
+    off += align_up(rows * dp * sizeof(float));
+    p.perm_off = off;
+    off += align_up(rows * sizeof(int32_t));
+    p.box_off = off;
+    off += align_up((size_t)p.ntiles * 2 * dp * sizeof(float));
+    p.bytes = off;
+    return p;
+}
+
+constexpr int kNumClasses = (kMaxD + 1) * 5;
+int class_id(int d, int kc) {
+    const int ki = kc == 0 ? 0 : kc == 5 ? 1 : kc == 10 ? 2 : kc == 20 ? 3 : 4;
+    return d * 5 + ki;
+}
+
+struct MetaLayout {
+    size_t table, order, unit_prefix, tile_prefix, counters, bytes;
+};
+
+MetaLayout meta_layout(int n_jobs) {
+    MetaLayout m{};
+    size_t off = 0;
+    m.table = off;
+    off += align_up((size_t)n_jobs * sizeof(DevJob));
+    m.order = off;
+    off += align_up((size_t)n_jobs * sizeof(int32_t));
+    m.unit_prefix = off;
+    off += align_up((size_t)(n_jobs + kNumClasses) * sizeof(int32_t));
+    m.tile_prefix = off;
+    off += align_up((size_t)(n_jobs + 1) * sizeof(int32_t));
+    m.counters = off;
+    off += align_up((size_t)kNumClasses * sizeof(int32_t));
+    m.bytes = off;
+    return m;
+}
+
+struct Tune {
+    int mode, split, index_dims, filter;
+};
+
+Tune resolve_tune(const snaps_tuning* t) {
+    Tune r{0, 0, 0, 0};
+    if (t) r = Tune{t->mode, t->split, t->index_dims, t->filter};
+    return r;
+}
+
+// Fill the device-side description of one job.
+DevJob make_devjob(const snaps_population* P, uint32_t mask, const JobPlan& p, float eps, const Tune& tn,
+                   char* ws_base) {
+    DevJob j;
+    std::memset(&j, 0, sizeof(j));
+    j.cols = P->cols;
+    j.ld = P->ld;
+    j.n = p.n;
+    j.d = p.d;
+    j.k = p.k;
+    j.ntiles = p.ntiles;
+    j.eps2 = eps > 0.f ? (float)((double)eps * (double)eps) : -1.f;
+    int c = tn.index_dims > 0 ? std::min(tn.index_dims, p.d) : std::min(p.d, kMaxIndexDims);
+    j.c = c;
+    int f = 0;
+    for (int b = 0; b < 32; ++b)
+        if ((mask >> b) & 1u) j.feat[f++] = b;
+    j.idbits = std::max(1, ceil_log2(p.n));
+    j.bits = std::max(1, (32 - j.idbits) / c);
+    if (j.bits * c > 32 - j.idbits) j.bits = (32 - j.idbits) / c;
+    if (tn.mode == 1) j.prune = 0;
+    else if (tn.mode == 2) j.prune = 1;
+    else j.prune = p.d <= 10 ? 1 : 0;
+    j.xs = reinterpret_cast<float*>(ws_base + p.xs_off);
+    j.perm = reinterpret_cast<int32_t*>(ws_base + p.perm_off);
+    j.boxes = reinterpret_cast<float*>(ws_base + p.box_off);
+    return j;
+}
+
+int choose_split(const Tune& tn, int64_t total_units, int cus) {
+    if (tn.split > 0) return tn.split;
+    // Aim for about eight wavefronts per SIMD (four SIMDs per CU).
+    const int64_t target = (int64_t)cus * 4 * 8;
+    int s = 1;
+    while (s < 8 && total_units * s < target) s <<= 1;
+    return s;
+}
+
+// Launch the join kernels of every class present; `units` is per class.
+int launch_joins(const Meta& meta, const std::vector<int>& class_of_slot, const std::vector<int>& cls_count,
+                 const std::vector<int>& cls_units, const std::vector<int>& cls_order_off,
+                 const std::vector<int>& cls_prefix_off, const Tune& tn, int cus, hipStream_t s) {
+    (void)class_of_slot;
+    int64_t all_units = 0;
+    for (int c = 0; c < kNumClasses; ++c) all_units += cls_units[c];
+    const int split = choose_split(tn, all_units, cus);
+    const int xf = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        if (cls_count[c] == 0) continue;
+        const int d = c / 5;
+        static const int kKc[5] = {0, 5, 10, 20, 32};
+        const int kc = kKc[c % 5];
+        JoinArgs a{};
+        a.table = meta.table;
+        a.order = meta.order + cls_order_off[c];
+        a.unit_prefix = meta.unit_prefix + cls_prefix_off[c];
+        a.n_class_jobs = cls_count[c];
+        a.total_units = cls_units[c];
+        a.counter = meta.counters + c;
+        a.split = split;
+        const int per_cu = join_blocks_per_cu(d, kc, xf, split);
+        if (per_cu <= 0) return fail(SNAPS_EDEVICE, "no occupancy for join kernel d=%d kc=%d split=%d", d, kc, split);
+        int grid = std::min<int64_t>((int64_t)per_cu * cus, cls_units[c]);
+        hipError_t e = launch_join(d, kc, xf, a, grid, s);
+        if (e != hipSuccess) return hip_fail(e, "join kernel launch");
+    }
+    return SNAPS_OK;
+}
+
+// Shared driver of every entry point: jobs already validated and planned.
+struct RunJob {
+    const snaps_population* pop;
+    uint32_t mask;
+    float eps;              // <= 0: no range join
+    JobPlan plan;
+    int32_t* eps_count;
+    float* eps_mean;
+    int32_t* indeg;
+    float* knn_mean;
+    int32_t* rank;
+    int32_t* knn_ids;
+    float* knn_dist;
+};
+
+size_t run_workspace(const std::vector<RunJob>& jobs) {
+    size_t b = meta_layout((int)jobs.size()).bytes;
+    for (const auto& j : jobs) b += j.plan.bytes;
+    return b;
+}
+
+std::vector<uint8_t>& staging() {
+    thread_local std::vector<uint8_t> buf;
+    return buf;
+}
+
+int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_bytes, hipStream_t s) {
+    const int n_jobs = (int)jobs.size();
+    const size_t need = run_workspace(jobs);
+    if (!ws && need > 0) return fail(SNAPS_EINVAL, "workspace is NULL (%zu bytes needed)", need);
+    if (ws_bytes < need) return fail(SNAPS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc != SNAPS_OK) return rc;
+
+    char* base = static_cast<char*>(ws);
+    const MetaLayout ml = meta_layout(n_jobs);
+    Meta meta{};
+    meta.table = reinterpret_cast<DevJob*>(base + ml.table);
+    meta.order = reinterpret_cast<int32_t*>(base + ml.order);
+    meta.unit_prefix = reinterpret_cast<int32_t*>(base + ml.unit_prefix);
+    meta.tile_prefix = reinterpret_cast<int32_t*>(base + ml.tile_prefix);
+    meta.counters = reinterpret_cast<int32_t*>(base + ml.counters);
+    meta.n_counters = kNumClasses;
+
+    std::vector<DevJob> table(n_jobs);
+    size_t off = ml.bytes;
+    int64_t total_tiles = 0;
+    std::vector<int32_t> tile_prefix(n_jobs + 1, 0);
+    for (int i = 0; i < n_jobs; ++i) {
+        const RunJob& r = jobs[i];
+        DevJob j = make_devjob(r.pop, r.mask, r.plan, r.eps, tn, base + off);
+        j.eps_count = r.eps_count;
+        j.eps_mean = r.eps_mean;
+        j.indeg = r.indeg;
+        j.knn_mean = r.knn_mean;
+        j.rank = r.rank;
+        j.knn_ids = r.knn_ids;
+        j.knn_dist = r.knn_dist;
+        table[i] = j;
+        off += r.plan.bytes;
+        total_tiles += r.plan.ntiles;
+        tile_prefix[i + 1] = (int32_t)total_tiles;
+    }
+    if (total_tiles > INT32_MAX / 2) return fail(SNAPS_EUNSUPPORTED, "too many tiles in one call");
+
+    // Group jobs into kernel classes (dimensionality, top-k capacity); within
+    // a class, the most expensive jobs (largest n) go first.
+    std::vector<int> cls_count(kNumClasses, 0), cls_units(kNumClasses, 0);
+    std::vector<int> cls_order_off(kNumClasses, 0), cls_prefix_off(kNumClasses, 0);
+    std::vector<std::vector<int>> members(kNumClasses);
+    for (int i = 0; i < n_jobs; ++i) members[class_id(jobs[i].plan.d, jobs[i].plan.kc)].push_back(i);
+    std::vector<int32_t> order;
+    std::vector<int32_t> unit_prefix;
+    order.reserve(n_jobs);
+    unit_prefix.reserve(n_jobs + kNumClasses);
+    for (int c = 0; c < kNumClasses; ++c) {
+        auto& m = members[c];
+        std::stable_sort(m.begin(), m.end(), [&](int a, int b) { return jobs[a].plan.n > jobs[b].plan.n; });
+        cls_count[c] = (int)m.size();
+        cls_order_off[c] = (int)order.size();
+        cls_prefix_off[c] = (int)unit_prefix.size();
+        int64_t acc = 0;
+        unit_prefix.push_back(0);
+        for (int i : m) {
+            order.push_back(i);
+            acc += jobs[i].plan.ntiles;
+            unit_prefix.push_back((int32_t)acc);
+        }
+        cls_units[c] = (int)acc;
+    }
+
+    hipError_t e;
+    if (n_jobs == 1) {
+        IndexArgs ia{};
+        ia.meta = meta;
+        ia.n_jobs = 1;
+        ia.seed = 1;
+        ia.single_units = table[0].ntiles;
+        ia.single = table[0];
+        // the single job's class arrays start at offset 0 of order / unit_prefix
+        const int c = class_id(jobs[0].plan.d, jobs[0].plan.kc);
+        cls_order_off.assign(kNumClasses, 0);
+        cls_prefix_off.assign(kNumClasses, 0);
+        (void)c;
+        e = launch_index_sort(ia, 1, s);
+        if (e != hipSuccess) return hip_fail(e, "index sort launch");
+    } else {
+        // One host-to-device copy of the metadata block (synchronous for
+        // pageable host memory, so the staging buffer can be reused).
+        auto& st = staging();
+        st.assign(ml.bytes, 0);
+        std::memcpy(st.data() + ml.table, table.data(), table.size() * sizeof(DevJob));
+        std::memcpy(st.data() + ml.order, order.data(), order.size() * sizeof(int32_t));
+        std::memcpy(st.data() + ml.unit_prefix, unit_prefix.data(), unit_prefix.size() * sizeof(int32_t));
+        std::memcpy(st.data() + ml.tile_prefix, tile_prefix.data(), tile_prefix.size() * sizeof(int32_t));
+        e = hipMemcpyAsync(base, st.data(), ml.bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "job table upload");
+        IndexArgs ia{};
+        ia.meta = meta;
+        ia.n_jobs = n_jobs;
+        ia.seed = 0;
+        e = launch_index_sort(ia, n_jobs, s);
+        if (e != hipSuccess) return hip_fail(e, "index sort launch");
+    }
+    e = launch_reorder(meta, n_jobs, (int32_t)total_tiles, s);
+    if (e != hipSuccess) return hip_fail(e, "reorder launch");
+    rc = launch_joins(meta, {}, cls_count, cls_units, cls_order_off, cls_prefix_off, tn, di.cus, s);
+    if (rc != SNAPS_OK) return rc;
+    bool any_rank = false;
+    for (const auto& j : jobs) any_rank |= (j.rank != nullptr);
+    if (any_rank) {
+        RankArgs ra{meta.table, n_jobs};
+        e = launch_rank(ra, s);
+        if (e != hipSuccess) return hip_fail(e, "rank launch");
+    }
+    return SNAPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* snaps_last_error(void) { return g_error.c_str(); }
+
+const char* snaps_version(void) { return "snaps-mi355x 0.1 (gfx950)"; }
+
+size_t snaps_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t k) {
+    if (n < 2 || n > kLdsSortMax) return 0;
+    if (op == SNAPS_OP_RANK) return 0;
+    if (d < 2 || d > kMaxD) return 0;
+    if (op == SNAPS_OP_EPS) k = 0;
+    else if (k < 1 || k > n - 1 || k > kMaxK) return 0;
+    if (op != SNAPS_OP_KNN && op != SNAPS_OP_EPS && op != SNAPS_OP_SCORES) return 0;
+    return meta_layout(1).bytes + plan_job(n, d, k).bytes;
+}
+
+static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, std::vector<RunJob>* out) {
+    if (n_jobs < 1) return fail(SNAPS_EINVAL, "n_jobs must be >= 1");
+    if (!jobs) return fail(SNAPS_EINVAL, "jobs is NULL");
+    out->clear();
+    out->reserve(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        const snaps_job& j = jobs[i];
+        int rc = check_population(j.pop, j.mask);
+        if (rc != SNAPS_OK) return fail(rc, "job %d: %s", i, g_error.c_str());
+        rc = check_k(j.pop->n, j.k);
+        if (rc != SNAPS_OK) return fail(rc, "job %d: %s", i, g_error.c_str());
+        rc = check_eps(j.eps);
+        if (rc != SNAPS_OK) return fail(rc, "job %d: %s", i, g_error.c_str());
+        if (!j.out.eps_count || !j.out.eps_mean || !j.out.indeg || !j.out.knn_mean)
+            return fail(SNAPS_EINVAL, "job %d: every score output array is required", i);
+        RunJob r{};
+        r.pop = j.pop;
+        r.mask = j.mask;
+        r.eps = j.eps;
+        r.plan = plan_job(j.pop->n, popcount32(j.mask), j.k);
+        r.eps_count = j.out.eps_count;
+        r.eps_mean = j.out.eps_mean;
+        r.indeg = j.out.indeg;
+        r.knn_mean = j.out.knn_mean;
+        r.rank = j.rank;
+        out->push_back(r);
+    }
+    return SNAPS_OK;
+}
+
+size_t snaps_outlier_scores_workspace(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune) {
+    std::vector<RunJob> rj;
+    if (check_tuning(tune) != SNAPS_OK) return 0;
+    if (collect_jobs(jobs, n_jobs, &rj) != SNAPS_OK) return 0;
+    return run_workspace(rj);
+}
+
+int snaps_knn_selfjoin(const snaps_population* P, uint32_t mask, int32_t k, int32_t* ids, float* dist,
+                       void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_population(P, mask);
+    if (rc != SNAPS_OK) return rc;
+    rc = check_k(P->n, k);
+    if (rc != SNAPS_OK) return rc;
+    if (!ids) return fail(SNAPS_EINVAL, "ids is NULL");
+    RunJob r{};
+    r.pop = P;
+    r.mask = mask;
+    r.eps = 0.f;
+    r.plan = plan_job(P->n, popcount32(mask), k);
+    r.knn_ids = ids;
+    r.knn_dist = dist;
+    return run({r}, Tune{0, 0, 0, 0}, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int snaps_eps_selfjoin(const snaps_population* P, uint32_t mask, float eps, int32_t* count, float* mean_dist,
+                       int64_t* pair_off, int32_t* pairs, int64_t pair_cap, void* ws, size_t ws_bytes,
+                       void* stream) {
+    int rc = check_population(P, mask);
+    if (rc != SNAPS_OK) return rc;
+    rc = check_eps(eps);
+    if (rc != SNAPS_OK) return rc;
+    if (!count) return fail(SNAPS_EINVAL, "count is NULL");
+    if (pair_off || pairs || pair_cap)
+        return fail(SNAPS_EUNSUPPORTED, "pair lists are not produced by this version");
+    if (!mean_dist) return fail(SNAPS_EINVAL, "mean_dist is NULL");
+    RunJob r{};
+    r.pop = P;
+    r.mask = mask;
+    r.eps = eps;
+    r.plan = plan_job(P->n, popcount32(mask), 0);
+    r.eps_count = count;
+    r.eps_mean = mean_dist;
+    return run({r}, Tune{0, 0, 0, 0}, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int snaps_outlier_scores(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune, void* ws,
+                         size_t ws_bytes, void* stream) {
+    int rc = check_tuning(tune);
+    if (rc != SNAPS_OK) return rc;
+    std::vector<RunJob> rj;
+    rc = collect_jobs(jobs, n_jobs, &rj);
+    if (rc != SNAPS_OK) return rc;
+    return run(rj, resolve_tune(tune), ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int snaps_rank(const int32_t* eps_count, const float* eps_mean, const int32_t* indeg, const float* knn_mean,
+               int64_t n, int32_t* rank, void* ws, size_t ws_bytes, void* stream) {
+    (void)ws;
+    (void)ws_bytes;
+    if (!eps_count || !eps_mean || !indeg || !knn_mean || !rank)
+        return fail(SNAPS_EINVAL, "every metric array and the rank output are required");
+    if (n < 1) return fail(SNAPS_EINVAL, "n must be >= 1");
+    if (n > kLdsSortMax) return fail(SNAPS_EUNSUPPORTED, "n = %lld exceeds this version's limit of %d", (long long)n, kLdsSortMax);
+    DevJob j;
+    std::memset(&j, 0, sizeof(j));
+    j.n = (int32_t)n;
+    j.eps_count = const_cast<int32_t*>(eps_count);
+    j.eps_mean = const_cast<float*>(eps_mean);
+    j.indeg = const_cast<int32_t*>(indeg);
+    j.knn_mean = const_cast<float*>(knn_mean);
+    j.rank = rank;
+    hipError_t e = launch_rank_single(j, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "rank launch");
+    return SNAPS_OK;
+}
+
+}  // extern "C"

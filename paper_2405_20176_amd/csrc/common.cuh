@@ -1,0 +1,102 @@
+// Device helpers shared by the libsnaps kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace snaps {
+
+// Pointers into read-only memory that every lane of a wavefront reads at the
+// same address.  Address space 4 (constant) tells the compiler the data is
+// invariant for the kernel's lifetime, so uniform reads become scalar loads
+// into SGPRs that every lane then uses as an operand.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+    return (cptr<T>)(p);
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Inclusive scan over a 64-lane wavefront.
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(v, o, 64);
+        if (lane >= o) v += y;
+    }
+    return v;
+}
+
+// Exclusive scan over the whole workgroup (blockDim.x a multiple of 64,
+// at most 1024).  tmp needs 17 ints of LDS.  Returns the exclusive prefix
+// and writes the workgroup total to *total.  Contains three barriers, so
+// consecutive calls may reuse tmp.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* tmp, int* total) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    int inc = wave_inclusive_scan(v);
+    if (lane == 63) tmp[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        int w = lane < nw ? tmp[lane] : 0;
+        int wi = wave_inclusive_scan(w);
+        if (lane < nw) tmp[lane] = wi - w;
+        if (lane == nw - 1) tmp[16] = wi;
+    }
+    __syncthreads();
+    const int tot = tmp[16];
+    const int base = tmp[wave];
+    __syncthreads();
+    *total = tot;
+    return inc - v + base;
+}
+
+// Ascending bitonic sort of P (a power of two) 32-bit keys in LDS by the
+// whole workgroup.  Ends with a barrier.
+__device__ __forceinline__ void bitonic_sort_lds(uint32_t* buf, int P) {
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int p = threadIdx.x; p < (P >> 1); p += blockDim.x) {
+                const int i = 2 * p - (p & (j - 1));
+                const int l = i + j;
+                const uint32_t a = buf[i];
+                const uint32_t b = buf[l];
+                const bool up = (i & k) == 0;
+                if ((a > b) == up) {
+                    buf[i] = b;
+                    buf[l] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__host__ __device__ inline int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace snaps

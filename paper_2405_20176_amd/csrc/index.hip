@@ -1,0 +1,195 @@
+// Index build of one (population, subspace) job: the grid index of the
+// paper (Sec. 3.8.1: objects indexed in c = min(d, 6) of the d dimensions),
+// laid out for a GPU that scans whole tiles of candidates.
+//
+//   1. k_index_sort (one workgroup per job): per-dimension mean and spread of
+//      the job's d columns; the c most spread dimensions are cut into 2^bits
+//      cells over mean +/- 3 sigma; every object gets the Morton (Z-order)
+//      interleaving of its c cell coordinates, packed above its id into one
+//      32-bit key; the keys are sorted in LDS.  Sorted position -> id is the
+//      permutation `perm`.
+//   2. k_reorder (one wavefront per tile of 64 positions): gathers the d
+//      subspace columns of every object in sorted order into a row-major
+//      array (plus the squared norm), pads the last tile with NaN rows, and
+//      records each tile's bounding box in all d dimensions.
+//
+// Any order of the objects gives the same join results (the join prunes a
+// tile only when its box is provably out of reach); the index order only
+// decides how much the join can skip.
+#include "snaps_internal.h"
+#include "common.cuh"
+
+#include <climits>
+
+namespace snaps {
+
+__global__ __launch_bounds__(kSortThreads) void k_index_sort(IndexArgs A) {
+    __shared__ uint32_t buf[kLdsSortMax];
+    __shared__ float red[2][16][kMaxD];     // per-wave partial sums / sums of squares
+    __shared__ int s_col[kMaxIndexDims];
+    __shared__ float s_lo[kMaxIndexDims];
+    __shared__ float s_scale[kMaxIndexDims];
+
+    DevJob J;
+    if (A.seed) {
+        J = A.single;
+        if (threadIdx.x == 0) {
+            *A.meta.table = A.single;
+            A.meta.order[0] = 0;
+            A.meta.unit_prefix[0] = 0;
+            A.meta.unit_prefix[1] = A.single_units;
+            A.meta.tile_prefix[0] = 0;
+            A.meta.tile_prefix[1] = A.single_units;
+        }
+    } else {
+        J = A.meta.table[blockIdx.x];
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < A.meta.n_counters) A.meta.counters[threadIdx.x] = 0;
+
+    const int n = J.n;
+    const int d = J.d;
+    const int c = J.c;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+
+    // Mean and spread of every dimension of the subspace.
+    float s[kMaxD], ss[kMaxD];
+#pragma unroll
+    for (int f = 0; f < kMaxD; ++f) { s[f] = 0.f; ss[f] = 0.f; }
+    for (int i = tid; i < n; i += blockDim.x) {
+#pragma unroll
+        for (int f = 0; f < kMaxD; ++f) {
+            if (f < d) {
+                const float v = J.cols[(int64_t)J.feat[f] * J.ld + i];
+                s[f] += v;
+                ss[f] = fmaf(v, v, ss[f]);
+            }
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < kMaxD; ++f) {
+        if (f < d) {
+            const float a = wave_sum(s[f]);
+            const float b = wave_sum(ss[f]);
+            if (lane == 0) { red[0][wave][f] = a; red[1][wave][f] = b; }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float mean[kMaxD], sd[kMaxD];
+        const int nw = blockDim.x >> 6;
+        for (int f = 0; f < d; ++f) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < nw; ++w) { a += red[0][w][f]; b += red[1][w][f]; }
+            const double m = a / n;
+            const double var = b / n - m * m;
+            mean[f] = (float)m;
+            sd[f] = var > 0.0 ? (float)sqrt(var) : 0.f;
+        }
+        // The c dimensions with the largest spread (lower index on ties).
+        unsigned used = 0;
+        for (int e = 0; e < c; ++e) {
+            int best = -1;
+            for (int f = 0; f < d; ++f) {
+                if ((used >> f) & 1u) continue;
+                if (best < 0 || sd[f] > sd[best]) best = f;
+            }
+            used |= 1u << best;
+            const float sg = sd[best];
+            const float lo = sg > 0.f ? mean[best] - 3.f * sg : mean[best] - 0.5f;
+            const float hi = sg > 0.f ? mean[best] + 3.f * sg : mean[best] + 0.5f;
+            s_col[e] = J.feat[best];
+            s_lo[e] = lo;
+            s_scale[e] = (float)(1u << J.bits) / (hi - lo);
+        }
+    }
+    __syncthreads();
+
+    const int P = next_pow2(n < 2 ? 2 : n);
+    const int bits = J.bits;
+    const uint32_t qmax = (1u << bits) - 1u;
+    for (int i = tid; i < P; i += blockDim.x) {
+        uint32_t packed = 0xFFFFFFFFu;
+        if (i < n) {
+            uint32_t qv[kMaxIndexDims];
+#pragma unroll
+            for (int e = 0; e < kMaxIndexDims; ++e) {
+                qv[e] = 0;
+                if (e < c) {
+                    const float v = J.cols[(int64_t)s_col[e] * J.ld + i];
+                    float t = (v - s_lo[e]) * s_scale[e];
+                    t = fminf(fmaxf(t, 0.f), (float)qmax);
+                    qv[e] = (uint32_t)t;
+                }
+            }
+            uint32_t key = 0;
+            for (int b = bits - 1; b >= 0; --b) {
+#pragma unroll
+                for (int e = 0; e < kMaxIndexDims; ++e)
+                    if (e < c) key = (key << 1) | ((qv[e] >> b) & 1u);
+            }
+            packed = (key << J.idbits) | (uint32_t)i;
+        }
+        buf[i] = packed;
+    }
+    __syncthreads();
+    bitonic_sort_lds(buf, P);
+    const uint32_t idmask = (J.idbits >= 32) ? 0xFFFFFFFFu : ((1u << J.idbits) - 1u);
+    for (int i = tid; i < n; i += blockDim.x) J.perm[i] = (int32_t)(buf[i] & idmask);
+}
+
+__global__ __launch_bounds__(64) void k_reorder(Meta m, int32_t n_jobs) {
+    const int u = blockIdx.x;
+    int lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (m.tile_prefix[mid] <= u) lo = mid; else hi = mid;
+    }
+    const DevJob J = m.table[lo];
+    const int t = u - m.tile_prefix[lo];
+    const int lane = threadIdx.x;
+    const int pos = t * kTile + lane;
+    const int n = J.n;
+    const int d = J.d;
+    const int dp = row_stride(d);
+    const bool valid = pos < n;
+    float* row = J.xs + (int64_t)pos * dp;
+    float* box = J.boxes + (int64_t)t * 2 * dp;
+    int id = INT32_MAX;
+    if (valid) id = J.perm[pos];
+    else J.perm[pos] = INT32_MAX;
+    if (valid && J.indeg) J.indeg[pos] = 0;
+    const float qnan = __int_as_float(0x7fc00000);
+    float norm = 0.f;
+#pragma unroll
+    for (int f = 0; f < kMaxD + 4; ++f) {
+        if (f < dp) {
+            float v;
+            if (f < d) {
+                v = valid ? J.cols[(int64_t)J.feat[f] * J.ld + id] : qnan;
+                if (valid) norm = fmaf(v, v, norm);
+                const float mn = wave_min(valid ? v : INFINITY);
+                const float mx = wave_max(valid ? v : -INFINITY);
+                if (lane == 0) { box[f] = mn; box[dp + f] = mx; }
+            } else {
+                v = 0.f;
+                if (lane == 0) { box[f] = 0.f; box[dp + f] = 0.f; }
+            }
+            row[f] = v;
+        }
+    }
+    row[d] = valid ? norm : qnan;
+}
+
+hipError_t launch_index_sort(const IndexArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_index_sort, dim3(grid), dim3(kSortThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reorder(const Meta& m, int32_t n_jobs, int32_t total_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_reorder, dim3(total_tiles), dim3(64), 0, s, m, n_jobs);
+    return hipGetLastError();
+}
+
+}  // namespace snaps

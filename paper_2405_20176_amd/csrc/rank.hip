@@ -1,0 +1,120 @@
+// Dense per-space rankings of the four outlier metrics (paper Sec. 3.4,
+// Tab. 2): r_i = the number of distinct metric values strictly more
+// outlying than object i's value, so rank 0 is the most outlying object and
+// equal values share a rank.
+//
+// One workgroup per (job, metric).  Each metric is mapped to a 32-bit key
+// whose ascending order is "more outlying first":
+//   eps_count, indeg   ascending integers, the value itself;
+//   eps_mean           descending, objects without any eps neighbour first;
+//   knn_mean           descending.
+// The keys are sorted in LDS, compacted to their distinct values, and every
+// object's rank is the position of its key among the distinct values
+// (binary search).
+#include "snaps_internal.h"
+#include "common.cuh"
+
+namespace snaps {
+
+namespace {
+
+// Monotone map of a float to an unsigned key (ascending float order).
+__device__ __forceinline__ uint32_t asc_key(float x) {
+    const uint32_t b = __float_as_uint(x);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ uint32_t metric_key(const DevJob& J, int metric, int i) {
+    switch (metric) {
+        case 0: return (uint32_t)J.eps_count[i];
+        case 1: return ~asc_key(J.eps_count[i] > 0 ? J.eps_mean[i] : INFINITY);
+        case 2: return (uint32_t)J.indeg[i];
+        default: return ~asc_key(J.knn_mean[i]);
+    }
+}
+
+}  // namespace
+
+struct RankLaunch {
+    RankArgs a;
+    int32_t seed;
+    DevJob single;
+};
+
+__global__ __launch_bounds__(kSortThreads) void k_rank(RankLaunch L) {
+    __shared__ uint32_t buf[kLdsSortMax];
+    __shared__ int tmp[17];
+    const DevJob J = L.seed ? L.single : L.a.table[blockIdx.x];
+    if (J.rank == nullptr) return;
+    const int metric = blockIdx.y;
+    const int n = J.n;
+    const int tid = threadIdx.x;
+    const int P = next_pow2(n < 2 ? 2 : n);
+
+    for (int i = tid; i < P; i += blockDim.x) buf[i] = i < n ? metric_key(J, metric, i) : 0xFFFFFFFFu;
+    __syncthreads();
+    bitonic_sort_lds(buf, P);
+
+    // Compact the sorted keys to their distinct values, in place: every thread
+    // first reads its block of E consecutive keys (and the key before it) into
+    // registers, then the blocks are written at their scanned offsets.
+    constexpr int kMaxE = kLdsSortMax / kSortThreads;
+    const int E = P >= (int)blockDim.x ? P / (int)blockDim.x : 1;
+    const int b0 = tid * E;
+    uint32_t vals[kMaxE];
+    bool flag[kMaxE];
+    int nflag = 0;
+    uint32_t prev = (b0 > 0 && b0 - 1 < P) ? buf[b0 - 1] : 0u;
+#pragma unroll
+    for (int e = 0; e < kMaxE; ++e) {
+        vals[e] = 0u;
+        flag[e] = false;
+        if (e < E) {
+            const int i = b0 + e;
+            if (i < n) {
+                vals[e] = buf[i];
+                flag[e] = (i == 0) || (vals[e] != prev);
+                prev = vals[e];
+                nflag += flag[e] ? 1 : 0;
+            }
+        }
+    }
+    int total = 0;
+    int pos = block_exclusive_scan(nflag, tmp, &total);
+#pragma unroll
+    for (int e = 0; e < kMaxE; ++e) {
+        if (flag[e]) buf[pos++] = vals[e];
+    }
+    __syncthreads();
+
+    int32_t* out = J.rank + (int64_t)metric * n;
+    for (int i = tid; i < n; i += blockDim.x) {
+        const uint32_t key = metric_key(J, metric, i);
+        int lo = 0, hi = total;          // first distinct value >= key
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (buf[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        out[i] = lo;
+    }
+}
+
+hipError_t launch_rank(const RankArgs& a, hipStream_t s) {
+    RankLaunch L{};
+    L.a = a;
+    L.seed = 0;
+    hipLaunchKernelGGL(k_rank, dim3(a.n_jobs, 4), dim3(kSortThreads), 0, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank_single(const DevJob& j, hipStream_t s) {
+    RankLaunch L{};
+    L.a.table = nullptr;
+    L.a.n_jobs = 1;
+    L.seed = 1;
+    L.single = j;
+    hipLaunchKernelGGL(k_rank, dim3(1, 4), dim3(kSortThreads), 0, s, L);
+    return hipGetLastError();
+}
+
+}  // namespace snaps

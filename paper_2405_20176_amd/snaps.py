@@ -1,0 +1,234 @@
+"""Python binding of libsnaps (ctypes), with the C ABI's names.
+
+Only argument marshalling happens here: device memory and streams come from
+PyTorch tensors, every computation runs in the library's HIP kernels.  The
+binding raises if the shared library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsnaps.so")
+
+SNAPS_OK = 0
+SNAPS_EINVAL = -1
+SNAPS_ENOMEM = -2
+SNAPS_EDEVICE = -3
+SNAPS_EUNSUPPORTED = -4
+OP_KNN, OP_EPS, OP_SCORES, OP_RANK = 0, 1, 2, 3
+MAX_N = 32768
+MAX_K = 32
+
+
+class SnapsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"snaps error {code}: {msg}")
+        self.code = code
+
+
+class c_population(ctypes.Structure):
+    _fields_ = [("cols", ctypes.c_void_p), ("ld", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("n_features", ctypes.c_int32)]
+
+
+class c_scores(ctypes.Structure):
+    _fields_ = [("eps_count", ctypes.c_void_p), ("eps_mean", ctypes.c_void_p),
+                ("indeg", ctypes.c_void_p), ("knn_mean", ctypes.c_void_p)]
+
+
+class c_job(ctypes.Structure):
+    _fields_ = [("pop", ctypes.POINTER(c_population)), ("mask", ctypes.c_uint32), ("k", ctypes.c_int32),
+                ("eps", ctypes.c_float), ("out", c_scores), ("rank", ctypes.c_void_p)]
+
+
+class c_tuning(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("split", ctypes.c_int32), ("index_dims", ctypes.c_int32),
+                ("filter", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsnaps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2405_20176_amd.build (no fallback exists)")
+    lib = ctypes.CDLL(path)
+    vp, sz, i32, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER
+    lib.snaps_last_error.restype = ctypes.c_char_p
+    lib.snaps_version.restype = ctypes.c_char_p
+    lib.snaps_workspace_bytes.restype = sz
+    lib.snaps_workspace_bytes.argtypes = [i32, i64, i32, i32]
+    lib.snaps_outlier_scores_workspace.restype = sz
+    lib.snaps_outlier_scores_workspace.argtypes = [P(c_job), i32, P(c_tuning)]
+    lib.snaps_knn_selfjoin.restype = ctypes.c_int
+    lib.snaps_knn_selfjoin.argtypes = [P(c_population), ctypes.c_uint32, i32, vp, vp, vp, sz, vp]
+    lib.snaps_eps_selfjoin.restype = ctypes.c_int
+    lib.snaps_eps_selfjoin.argtypes = [P(c_population), ctypes.c_uint32, ctypes.c_float, vp, vp, vp, vp, i64,
+                                       vp, sz, vp]
+    lib.snaps_outlier_scores.restype = ctypes.c_int
+    lib.snaps_outlier_scores.argtypes = [P(c_job), i32, P(c_tuning), vp, sz, vp]
+    lib.snaps_rank.restype = ctypes.c_int
+    lib.snaps_rank.argtypes = [vp, vp, vp, vp, i64, vp, vp, sz, vp]
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load_library().snaps_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != SNAPS_OK:
+        raise SnapsError(rc, last_error())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Population:
+    """A resident population: feature-major float32 columns [F, ld] on the
+    GPU, n objects (values normalised to [0, 1])."""
+
+    def __init__(self, cols: torch.Tensor, n: int):
+        if cols.dtype != torch.float32 or cols.dim() != 2 or not cols.is_cuda or not cols.is_contiguous():
+            raise ValueError("cols must be a contiguous float32 CUDA tensor [n_features, ld]")
+        self.cols = cols
+        self.n = int(n)
+        self.c = c_population(cols.data_ptr(), cols.shape[1], self.n, cols.shape[0])
+
+    @classmethod
+    def from_rows(cls, x, device="cuda") -> "Population":
+        """Upload a row-major [n, F] float32 array as feature-major columns
+        (leading dimension rounded up to 64)."""
+        x = torch.as_tensor(x, dtype=torch.float32)
+        n, f = x.shape
+        ld = (n + 63) // 64 * 64
+        cols = torch.zeros((f, ld), dtype=torch.float32)
+        cols[:, :n] = x.T
+        return cls(cols.to(device).contiguous(), n)
+
+
+def tuning(mode=0, split=0, index_dims=0, filter=0) -> c_tuning:
+    t = c_tuning()
+    t.mode, t.split, t.index_dims, t.filter = mode, split, index_dims, filter
+    return t
+
+
+def snaps_workspace_bytes(op: int, n: int, d: int, k: int) -> int:
+    return int(load_library().snaps_workspace_bytes(op, n, d, k))
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def snaps_knn_selfjoin(pop: Population, mask: int, k: int, ids: torch.Tensor, dist: Optional[torch.Tensor] = None,
+                       ws: Optional[torch.Tensor] = None, stream=None):
+    lib = load_library()
+    d = bin(int(mask)).count("1")
+    need = lib.snaps_workspace_bytes(OP_KNN, pop.n, d, k)
+    if ws is None:
+        ws = _workspace(need, pop.cols.device)
+    _check(lib.snaps_knn_selfjoin(ctypes.byref(pop.c), int(mask), int(k), _ptr(ids), _ptr(dist), _ptr(ws),
+                                  ws.numel(), _stream(stream)))
+
+
+def snaps_eps_selfjoin(pop: Population, mask: int, eps: float, count: torch.Tensor, mean_dist: torch.Tensor,
+                       ws: Optional[torch.Tensor] = None, stream=None):
+    lib = load_library()
+    d = bin(int(mask)).count("1")
+    need = lib.snaps_workspace_bytes(OP_EPS, pop.n, d, 0)
+    if ws is None:
+        ws = _workspace(need, pop.cols.device)
+    _check(lib.snaps_eps_selfjoin(ctypes.byref(pop.c), int(mask), float(eps), _ptr(count), _ptr(mean_dist),
+                                  None, None, 0, _ptr(ws), ws.numel(), _stream(stream)))
+
+
+@dataclass
+class Job:
+    """One (population, subspace) job and its output tensors (length n)."""
+    pop: Population
+    mask: int
+    k: int
+    eps: float
+    eps_count: torch.Tensor
+    eps_mean: torch.Tensor
+    indeg: torch.Tensor
+    knn_mean: torch.Tensor
+    rank: Optional[torch.Tensor] = None      # [4, n] int32
+
+    @classmethod
+    def alloc(cls, pop: Population, mask: int, k: int, eps: float, with_rank: bool = True) -> "Job":
+        dev = pop.cols.device
+        n = pop.n
+        return cls(pop, int(mask), int(k), float(eps),
+                   torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
+                   torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
+                   torch.empty((4, n), dtype=torch.int32, device=dev) if with_rank else None)
+
+
+def _c_jobs(jobs: Sequence[Job]):
+    arr = (c_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i].pop = ctypes.pointer(j.pop.c)
+        arr[i].mask = j.mask
+        arr[i].k = j.k
+        arr[i].eps = j.eps
+        arr[i].out = c_scores(j.eps_count.data_ptr(), j.eps_mean.data_ptr(), j.indeg.data_ptr(),
+                              j.knn_mean.data_ptr())
+        arr[i].rank = None if j.rank is None else j.rank.data_ptr()
+    return arr
+
+
+def snaps_outlier_scores_workspace(jobs: Sequence[Job], tune: Optional[c_tuning] = None) -> int:
+    lib = load_library()
+    arr = _c_jobs(jobs)
+    return int(lib.snaps_outlier_scores_workspace(arr, len(jobs), None if tune is None else ctypes.byref(tune)))
+
+
+def snaps_outlier_scores(jobs: Sequence[Job], tune: Optional[c_tuning] = None, ws: Optional[torch.Tensor] = None,
+                         stream=None):
+    lib = load_library()
+    arr = _c_jobs(jobs)
+    tp = None if tune is None else ctypes.byref(tune)
+    need = lib.snaps_outlier_scores_workspace(arr, len(jobs), tp)
+    if need == 0:
+        # let the library report why
+        _check(lib.snaps_outlier_scores(arr, len(jobs), tp, None, 0, _stream(stream)))
+    if ws is None:
+        ws = _workspace(need, jobs[0].pop.cols.device)
+    _check(lib.snaps_outlier_scores(arr, len(jobs), tp, _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def snaps_rank(eps_count: torch.Tensor, eps_mean: torch.Tensor, indeg: torch.Tensor, knn_mean: torch.Tensor,
+               rank: torch.Tensor, stream=None):
+    lib = load_library()
+    n = eps_count.numel()
+    _check(lib.snaps_rank(_ptr(eps_count), _ptr(eps_mean), _ptr(indeg), _ptr(knn_mean), n, _ptr(rank), None, 0,
+                          _stream(stream)))
+
+
+def score_space(pop: Population, mask: int, k: int, eps: float, tune: Optional[c_tuning] = None,
+                with_rank: bool = True) -> Job:
+    """Convenience: allocate the outputs and run one job."""
+    job = Job.alloc(pop, mask, k, eps, with_rank)
+    snaps_outlier_scores([job], tune)
+    return job

@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function the public header declares, sizes workspaces, and rejects
+invalid arguments before touching a device."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "snaps.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(snaps_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2405_20176_amd import snaps
+    return snaps.load_library()
+
+
+def test_header_declares_the_four_entry_points():
+    names = declared_functions()
+    for f in ("snaps_knn_selfjoin", "snaps_eps_selfjoin", "snaps_outlier_scores", "snaps_rank"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_empty_error(lib):
+    assert b"gfx950" in lib.snaps_version()
+
+
+def test_workspace_sizes(lib):
+    from paper_2405_20176_amd.snaps import OP_EPS, OP_KNN, OP_RANK, OP_SCORES
+    a = lib.snaps_workspace_bytes(OP_SCORES, 31693, 15, 10)
+    b = lib.snaps_workspace_bytes(OP_SCORES, 31693, 2, 10)
+    assert a > b > 31693 * 4
+    assert lib.snaps_workspace_bytes(OP_SCORES, 1, 3, 1) == 0          # n < 2
+    assert lib.snaps_workspace_bytes(OP_KNN, 100, 3, 100) == 0         # k > n-1
+    assert lib.snaps_workspace_bytes(OP_KNN, 100, 17, 5) == 0          # d > 16
+    assert lib.snaps_workspace_bytes(OP_EPS, 100, 3, 0) > 0
+    assert lib.snaps_workspace_bytes(OP_RANK, 100, 0, 0) == 0
+    assert lib.snaps_workspace_bytes(OP_SCORES, 40000, 3, 5) == 0      # beyond this version's n limit
+
+
+def _pop(n=100, f=15):
+    from paper_2405_20176_amd.snaps import c_population
+    return c_population(0x1000, 128, n, f)   # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("mask,k,expect", [
+    (0b1, 5, -1),            # one feature
+    (1 << 15, 5, -1),        # beyond n_features
+    (0b111, 0, -1),          # k < 1
+    (0b111, 100, -1),        # k > n - 1
+    (0b111, 40, -4),         # k beyond the supported 32
+])
+def test_knn_validation(lib, mask, k, expect):
+    p = _pop()
+    ids = ctypes.c_void_p(0x2000)
+    rc = lib.snaps_knn_selfjoin(ctypes.byref(p), mask, k, ids, None, None, 0, None)
+    assert rc == expect, lib.snaps_last_error()
+    assert lib.snaps_last_error()
+
+
+def test_eps_validation(lib):
+    p = _pop()
+    c = ctypes.c_void_p(0x2000)
+    for eps in (0.0, -1.0, float("inf"), float("nan")):
+        assert lib.snaps_eps_selfjoin(ctypes.byref(p), 0b11, eps, c, c, None, None, 0, None, 0, None) == -1
+    # pair lists are not produced by this version
+    assert lib.snaps_eps_selfjoin(ctypes.byref(p), 0b11, 0.1, c, c, c, c, 10, None, 0, None) == -4
+
+
+def test_population_validation(lib):
+    from paper_2405_20176_amd.snaps import c_population
+    c = ctypes.c_void_p(0x2000)
+    bad = [c_population(0, 128, 100, 15), c_population(0x1000, 50, 100, 15), c_population(0x1000, 128, 1, 15),
+           c_population(0x1000, 128, 100, 1), c_population(0x1000, 128, 100, 33)]
+    for p in bad:
+        assert lib.snaps_knn_selfjoin(ctypes.byref(p), 0b11, 1, c, None, None, 0, None) == -1
+    big = c_population(0x1000, 1 << 20, 1 << 20, 15)
+    assert lib.snaps_knn_selfjoin(ctypes.byref(big), 0b11, 1, c, None, None, 0, None) == -4
+
+
+def test_outlier_scores_validation(lib):
+    from paper_2405_20176_amd.snaps import c_job, c_scores, c_tuning
+    p = _pop()
+    job = c_job()
+    job.pop = ctypes.pointer(p)
+    job.mask, job.k, job.eps = 0b111, 5, 0.1
+    job.out = c_scores(0x10, 0x20, 0x30, 0x40)
+    assert lib.snaps_outlier_scores(ctypes.byref(job), 0, None, None, 0, None) == -1      # n_jobs = 0
+    bad = c_job.from_buffer_copy(job)
+    bad.out = c_scores(0, 0x20, 0x30, 0x40)
+    assert lib.snaps_outlier_scores(ctypes.byref(bad), 1, None, None, 0, None) == -1      # missing output
+    t = c_tuning()
+    t.split = 3
+    assert lib.snaps_outlier_scores(ctypes.byref(job), 1, ctypes.byref(t), None, 0, None) == -1
+    t = c_tuning()
+    need = lib.snaps_outlier_scores_workspace(ctypes.byref(job), 1, ctypes.byref(t))
+    assert need > 0
+    # a workspace that is too small is reported before any device work
+    rc = lib.snaps_outlier_scores(ctypes.byref(job), 1, ctypes.byref(t), ctypes.c_void_p(0x1000), need - 1, None)
+    assert rc == -2, lib.snaps_last_error()
+
+
+def test_rank_validation(lib):
+    c = ctypes.c_void_p(0x2000)
+    assert lib.snaps_rank(None, c, c, c, 10, c, None, 0, None) == -1
+    assert lib.snaps_rank(c, c, c, c, 0, c, None, 0, None) == -1
+    assert lib.snaps_rank(c, c, c, c, 1 << 20, c, None, 0, None) == -4

@@ -1,0 +1,252 @@
+"""GPU parity: libsnaps (through its C ABI) against the float64 oracle.
+
+Every case runs the HIP path on seeded synthetic inputs and compares element
+by element with the oracle under the acceptance rule of ``tests/parity.py``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from oracle import c_oracle as C
+import snaps_synth as G
+from tests.golden import exact_fp32_variant, load_tab2
+from tests.parity import TAU, check_knn, check_scores, self_ranks
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_20176_amd import snaps
+    snaps.load_library()
+    return snaps
+
+
+def run_gpu(S, x, mask, k, eps, tune=None, with_rank=True):
+    pop = S.Population.from_rows(x)
+    job = S.Job.alloc(pop, mask, k, eps, with_rank)
+    S.snaps_outlier_scores([job], tune)
+    torch.cuda.synchronize()
+    out = {key: getattr(job, key).cpu().numpy() for key in ("eps_count", "eps_mean", "indeg", "knn_mean")}
+    out["rank"] = job.rank.cpu().numpy() if with_rank else None
+    return out
+
+
+def run_oracle(x, mask, k, eps):
+    xs = O.project(x, mask).astype(np.float32)
+    return C.outlier_scores(xs, k, float(eps), band=(float(eps) * (1 - TAU), float(eps) * (1 + TAU)))
+
+
+def full_mask(f):
+    return (1 << f) - 1
+
+
+def test_tab2_worked_example_exact(S):
+    coords, _, k, table, _ = load_tab2()
+    x = exact_fp32_variant(coords)
+    eps = np.float32(67.0 / 512.0)
+    g = run_gpu(S, x, 0b11, k, float(eps))
+    np.testing.assert_array_equal(g["eps_count"], table[:, 0])
+    np.testing.assert_array_equal(np.round(g["eps_mean"].astype(np.float64) * 5.12, 4), table[:, 2])
+    np.testing.assert_array_equal(g["indeg"], table[:, 4])
+    np.testing.assert_array_equal(np.round(g["knn_mean"].astype(np.float64) * 5.12, 4), table[:, 6])
+    for t, col in enumerate((1, 3, 5, 7)):
+        np.testing.assert_array_equal(g["rank"][t], table[:, col])
+    ids = torch.empty((10, k), dtype=torch.int32, device="cuda")
+    dist = torch.empty((10, k), dtype=torch.float32, device="cuda")
+    pop = S.Population.from_rows(x)
+    S.snaps_knn_selfjoin(pop, 0b11, k, ids, dist)
+    torch.cuda.synchronize()
+    _, _, _, _, edges = load_tab2()
+    for i, nb in edges.items():
+        assert set(ids[i].cpu().tolist()) == nb
+
+
+@pytest.fixture(scope="module")
+def c0():
+    x, k = G.gen_c0()
+    return x, k, O.eps_exact_mean_count(x, 10)
+
+
+@pytest.mark.parametrize("split", [1, 2, 4, 8])
+@pytest.mark.parametrize("mode", [1, 2])
+def test_c0_parity(S, c0, split, mode):
+    x, k, eps = c0
+    g = run_gpu(S, x, 0b111, k, float(eps), S.tuning(mode=mode, split=split))
+    ora = run_oracle(x, 0b111, k, eps)
+    rep = check_scores(g, ora, k, float(eps), label=f"C0 split={split} mode={mode}")
+    # eps is the midpoint of two pair distances closer than tau: those two
+    # pairs (four objects) sit inside the boundary band
+    assert rep["knn_exempt"] <= 0.01 * x.shape[0] and rep["eps_exempt"] <= 0.01 * x.shape[0]
+
+
+def test_pruning_and_split_invariance_bitwise(S, c0):
+    """Skipping provably out-of-reach tiles never changes a result; the split
+    of candidates over wavefronts changes only the eps-mean summation order."""
+    x, k, eps = c0
+    for split in (1, 4):
+        a = run_gpu(S, x, 0b111, k, float(eps), S.tuning(mode=1, split=split))
+        b = run_gpu(S, x, 0b111, k, float(eps), S.tuning(mode=2, split=split))
+        for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+            np.testing.assert_array_equal(a[key], b[key], err_msg=f"{key} split={split}")
+    a = run_gpu(S, x, 0b111, k, float(eps), S.tuning(split=1))
+    b = run_gpu(S, x, 0b111, k, float(eps), S.tuning(split=8))
+    for key in ("eps_count", "indeg", "knn_mean"):
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+def test_determinism(S, c0):
+    x, k, eps = c0
+    a = run_gpu(S, x, 0b111, k, float(eps))
+    b = run_gpu(S, x, 0b111, k, float(eps))
+    for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+@pytest.mark.parametrize("n", [2, 3, 17, 63, 64, 65, 129, 1000])
+def test_ragged_and_tiny_sizes(S, n):
+    rng = np.random.default_rng(n)
+    x = rng.random((n, 4)).astype(np.float32)
+    for k in sorted({1, min(5, n - 1), min(n - 1, 32)}):
+        eps = 0.3
+        g = run_gpu(S, x, 0b1011, k, eps)
+        check_scores(g, run_oracle(x, 0b1011, k, eps), k, eps, label=f"n={n} k={k}")
+
+
+@pytest.mark.parametrize("d", list(range(2, 17)))
+def test_every_dimensionality(S, d):
+    rng = np.random.default_rng(100 + d)
+    x = rng.random((700, 16)).astype(np.float32)
+    mask = int(sum(1 << f for f in rng.choice(16, size=d, replace=False)))
+    for k in (1, 5, 10, 20, 32):
+        eps = 0.12 * math.sqrt(d)
+        g = run_gpu(S, x, mask, k, eps, S.tuning(split=2))
+        check_scores(g, run_oracle(x, mask, k, eps), k, eps, label=f"d={d} k={k}")
+
+
+def test_duplicates_and_ties(S):
+    rng = np.random.default_rng(7)
+    base = (rng.integers(0, 4, size=(40, 3)) / 4.0).astype(np.float32)   # many exact duplicates
+    x = np.concatenate([base, base, np.full((30, 3), 0.5, np.float32)])
+    for k in (1, 3, 10, 32):
+        g = run_gpu(S, x, 0b111, k, 0.25)
+        ora = run_oracle(x, 0b111, k, 0.25)
+        check_scores(g, ora, k, 0.25, label=f"dups k={k}")
+    m = 9
+    same = np.full((m, 2), 0.25, np.float32)
+    g = run_gpu(S, same, 0b11, 3, 0.01)
+    np.testing.assert_array_equal(g["indeg"], [m - 1, m - 1, m - 1, 3, 0, 0, 0, 0, 0])
+    np.testing.assert_array_equal(g["eps_count"], m - 1)
+    np.testing.assert_array_equal(g["eps_mean"], 0.0)
+
+
+def test_degenerate_eps_and_k(S):
+    rng = np.random.default_rng(3)
+    n = 33
+    x = rng.random((n, 3)).astype(np.float32)
+    g = run_gpu(S, x, 0b111, n - 1, 2.0)
+    assert (g["eps_count"] == n - 1).all()
+    assert (g["indeg"] == n - 1).all()
+    np.testing.assert_allclose(g["eps_mean"], g["knn_mean"], rtol=2e-6)
+    g = run_gpu(S, x, 0b111, 2, 1e-6)
+    assert (g["eps_count"] == 0).all() and (g["eps_mean"] == 0).all() and (g["rank"][0] == 0).all()
+
+
+def test_isolated_points_rank_first(S):
+    x, corners = G.gen_isolated_fixture()
+    g = run_gpu(S, x, 0b111, 5, 0.1)
+    assert (g["eps_count"][corners] == 0).all() and (g["rank"][0][corners] == 0).all()
+    assert (g["rank"][1][corners] == 0).all() and (g["rank"][2][corners] == 0).all()
+    assert sorted(g["rank"][3][corners].tolist()) == list(range(len(corners)))
+
+
+def test_batched_equals_single(S):
+    rng = np.random.default_rng(12)
+    x = rng.random((3000, 15)).astype(np.float32)
+    pop = S.Population.from_rows(x)
+    specs = []
+    for i in range(24):
+        d = int(rng.integers(2, 16))
+        mask = int(sum(1 << f for f in rng.choice(15, size=d, replace=False)))
+        k = int(rng.choice([5, 10, 20]))
+        specs.append((mask, k, 0.05 * math.sqrt(d)))
+    tune = S.tuning(split=1)
+    jobs = [S.Job.alloc(pop, m, k, e) for m, k, e in specs]
+    S.snaps_outlier_scores(jobs, tune)
+    torch.cuda.synchronize()
+    for (m, k, e), job in zip(specs, jobs):
+        single = S.Job.alloc(pop, m, k, e)
+        S.snaps_outlier_scores([single], tune)
+        torch.cuda.synchronize()
+        for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+            assert torch.equal(getattr(job, key), getattr(single, key)), f"{key} mask={m:x}"
+    for (m, k, e), job in list(zip(specs, jobs))[:4]:
+        g = {key: getattr(job, key).cpu().numpy() for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank")}
+        check_scores(g, run_oracle(x, m, k, e), k, e, label=f"batched mask={m:x}")
+
+
+def test_knn_and_eps_entry_points(S):
+    rng = np.random.default_rng(5)
+    x = rng.random((1500, 6)).astype(np.float32)
+    pop = S.Population.from_rows(x)
+    k, mask, eps = 10, 0b110101, 0.2
+    ids = torch.empty((1500, k), dtype=torch.int32, device="cuda")
+    dist = torch.empty((1500, k), dtype=torch.float32, device="cuda")
+    S.snaps_knn_selfjoin(pop, mask, k, ids, dist)
+    cnt = torch.empty(1500, dtype=torch.int32, device="cuda")
+    mean = torch.empty(1500, dtype=torch.float32, device="cuda")
+    S.snaps_eps_selfjoin(pop, mask, eps, cnt, mean)
+    torch.cuda.synchronize()
+    ora = run_oracle(x, mask, k, eps)
+    check_knn(ids.cpu().numpy(), dist.cpu().numpy(), ora, k)
+    exempt = ora["band"] > 0
+    assert ((cnt.cpu().numpy() == ora["eps_count"]) | exempt).all()
+    rel = np.abs(mean.cpu().numpy() - ora["eps_mean"]) / np.maximum(ora["eps_mean"], 1e-30)
+    assert ((rel <= TAU) | exempt | (ora["eps_mean"] == 0)).all()
+
+
+def test_rank_entry_point(S):
+    rng = np.random.default_rng(9)
+    for n in (1, 2, 100, 4097, 32768):
+        cnt = rng.integers(0, 7, size=n).astype(np.int32)
+        mean = np.where(cnt > 0, rng.integers(0, 50, size=n) / 7.0, 0.0).astype(np.float32)
+        deg = rng.integers(0, 9, size=n).astype(np.int32)
+        km = (rng.integers(0, 1000, size=n) / 13.0).astype(np.float32)
+        rank = torch.empty((4, n), dtype=torch.int32, device="cuda")
+        t = [torch.from_numpy(a).cuda() for a in (cnt, mean, deg, km)]
+        S.snaps_rank(*t, rank)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(rank.cpu().numpy(), self_ranks(cnt, mean, deg, km))
+
+
+@pytest.fixture(scope="module")
+def c1():
+    x, masks, k = G.gen_c1()
+    try:
+        eps = G.load_c1_eps()
+    except (OSError, ValueError):
+        eps = None
+    return x, masks, k, eps
+
+
+@pytest.mark.parametrize("which", [0, 104, 105, 560, 5000, 20000, 32751])
+def test_c1_full_size_spaces(S, c1, which):
+    """Spaces of the SNAPShot1-shaped population at its full size, with the
+    stored per-space eps (oracle-computed)."""
+    x, masks, k, eps_tab = c1
+    mask = int(masks[which])
+    if eps_tab is not None:
+        eps = float(eps_tab[which])
+    else:
+        eps = float(O.eps_sampled_mean_count(O.project(x, mask), 10, 128, seed=mask))
+    g = run_gpu(S, x, mask, k, eps)
+    rep = check_scores(g, run_oracle(x, mask, k, eps), k, eps, label=f"C1 space {which}")
+    assert rep["knn_exempt"] < 0.01 * x.shape[0]
