@@ -94,6 +94,11 @@ typedef struct {
                                indeg, knn_mean), 0 = most outlying */
 } snaps_job;
 
+/* Passes of snaps_outlier_scores (snaps_tuning.passes). */
+#define SNAPS_PASS_INDEX 1   /* per-job index: sort by cell key, reorder into tiles, tile boxes */
+#define SNAPS_PASS_JOIN 2    /* fused kNN + eps join and the four metrics */
+#define SNAPS_PASS_RANK 4    /* dense rankings */
+
 /* Optional tuning (NULL or zero fields = automatic). */
 typedef struct {
     int32_t mode;           /* 0 auto, 1 brute force over every candidate tile,
@@ -102,7 +107,15 @@ typedef struct {
     int32_t index_dims;     /* 0 auto (min(d, 6), as Sec. 3.8.1), else 1..min(d, 6) */
     int32_t filter;         /* 0 auto, 1 direct distance form only,
                                2 expanded-form prefilter with exact direct recheck */
-    int32_t reserved[4];    /* must be 0 */
+    int32_t passes;         /* 0 = all; else a mask of SNAPS_PASS_*.  A call that runs the join
+                               or rank pass without the index pass must follow a call with the
+                               same jobs and workspace that ran the earlier passes. */
+    int32_t reserved[3];    /* must be 0 */
+    uint64_t* stats;        /* optional device uint64[4], accumulated (never cleared) by the
+                               join pass: [0] query-candidate pairs evaluated, [1] candidate
+                               tiles scanned, [2] candidate tiles skipped, [3] pairs evaluated
+                               times the subspace dimensionality (3x this is the float32
+                               operation count of the distance evaluations) */
 } snaps_tuning;
 
 /* Operation codes of snaps_workspace_bytes. */

@@ -84,7 +84,8 @@ int check_tuning(const snaps_tuning* t) {
         return fail(SNAPS_EINVAL, "tuning.split must be 0, 1, 2, 4 or 8");
     if (t->index_dims < 0 || t->index_dims > kMaxIndexDims) return fail(SNAPS_EINVAL, "tuning.index_dims must be in [0, 6]");
     if (t->filter < 0 || t->filter > 2) return fail(SNAPS_EINVAL, "tuning.filter must be 0, 1 or 2");
-    for (int i = 0; i < 4; ++i)
+    if (t->passes < 0 || t->passes > 7) return fail(SNAPS_EINVAL, "tuning.passes must be a mask of SNAPS_PASS_*");
+    for (int i = 0; i < 3; ++i)
         if (t->reserved[i] != 0) return fail(SNAPS_EINVAL, "tuning.reserved must be zero");
     return SNAPS_OK;
 }
@@ -167,12 +168,20 @@ MetaLayout meta_layout(int n_jobs) {
 }
 
 struct Tune {
-    int mode, split, index_dims, filter;
+    int mode = 0, split = 0, index_dims = 0, filter = 0, passes = 7;
+    unsigned long long* stats = nullptr;
 };
 
 Tune resolve_tune(const snaps_tuning* t) {
-    Tune r{0, 0, 0, 0};
-    if (t) r = Tune{t->mode, t->split, t->index_dims, t->filter};
+    Tune r;
+    if (t) {
+        r.mode = t->mode;
+        r.split = t->split;
+        r.index_dims = t->index_dims;
+        r.filter = t->filter;
+        r.passes = t->passes ? t->passes : 7;
+        r.stats = reinterpret_cast<unsigned long long*>(t->stats);
+    }
     return r;
 }
 
@@ -223,6 +232,8 @@ int launch_joins(const Meta& meta, const std::vector<int>& class_of_slot, const 
     for (int c = 0; c < kNumClasses; ++c) all_units += cls_units[c];
     const int split = choose_split(tn, all_units, cus);
     const int xf = 0;
+    hipError_t fe = launch_fill_i32(meta.counters, meta.n_counters, 0, s);
+    if (fe != hipSuccess) return hip_fail(fe, "counter reset");
     for (int c = 0; c < kNumClasses; ++c) {
         if (cls_count[c] == 0) continue;
         const int d = c / 5;
@@ -236,6 +247,7 @@ int launch_joins(const Meta& meta, const std::vector<int>& class_of_slot, const 
         a.total_units = cls_units[c];
         a.counter = meta.counters + c;
         a.split = split;
+        a.stats = tn.stats;
         const int per_cu = join_blocks_per_cu(d, kc, xf, split);
         if (per_cu <= 0) return fail(SNAPS_EDEVICE, "no occupancy for join kernel d=%d kc=%d split=%d", d, kc, split);
         int grid = std::min<int64_t>((int64_t)per_cu * cus, cls_units[c]);
@@ -338,7 +350,12 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
     }
 
     hipError_t e;
-    if (n_jobs == 1) {
+    const bool do_index = (tn.passes & SNAPS_PASS_INDEX) != 0;
+    const bool do_join = (tn.passes & SNAPS_PASS_JOIN) != 0;
+    const bool do_rank = (tn.passes & SNAPS_PASS_RANK) != 0;
+    if (n_jobs == 1 && !do_index) {
+        // metadata of a single job is written by the index pass; later passes reuse it
+    } else if (n_jobs == 1) {
         IndexArgs ia{};
         ia.meta = meta;
         ia.n_jobs = 1;
@@ -363,20 +380,26 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         std::memcpy(st.data() + ml.tile_prefix, tile_prefix.data(), tile_prefix.size() * sizeof(int32_t));
         e = hipMemcpyAsync(base, st.data(), ml.bytes, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "job table upload");
-        IndexArgs ia{};
-        ia.meta = meta;
-        ia.n_jobs = n_jobs;
-        ia.seed = 0;
-        e = launch_index_sort(ia, n_jobs, s);
-        if (e != hipSuccess) return hip_fail(e, "index sort launch");
     }
-    e = launch_reorder(meta, n_jobs, (int32_t)total_tiles, s);
-    if (e != hipSuccess) return hip_fail(e, "reorder launch");
-    rc = launch_joins(meta, {}, cls_count, cls_units, cls_order_off, cls_prefix_off, tn, di.cus, s);
-    if (rc != SNAPS_OK) return rc;
+    if (do_index) {
+        if (n_jobs > 1) {
+            IndexArgs ia{};
+            ia.meta = meta;
+            ia.n_jobs = n_jobs;
+            ia.seed = 0;
+            e = launch_index_sort(ia, n_jobs, s);
+            if (e != hipSuccess) return hip_fail(e, "index sort launch");
+        }
+        e = launch_reorder(meta, n_jobs, (int32_t)total_tiles, s);
+        if (e != hipSuccess) return hip_fail(e, "reorder launch");
+    }
+    if (do_join) {
+        rc = launch_joins(meta, {}, cls_count, cls_units, cls_order_off, cls_prefix_off, tn, di.cus, s);
+        if (rc != SNAPS_OK) return rc;
+    }
     bool any_rank = false;
     for (const auto& j : jobs) any_rank |= (j.rank != nullptr);
-    if (any_rank) {
+    if (do_rank && any_rank) {
         RankArgs ra{meta.table, n_jobs};
         e = launch_rank(ra, s);
         if (e != hipSuccess) return hip_fail(e, "rank launch");

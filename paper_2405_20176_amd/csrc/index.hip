@@ -182,6 +182,17 @@ __global__ __launch_bounds__(64) void k_reorder(Meta m, int32_t n_jobs) {
     row[d] = valid ? norm : qnan;
 }
 
+__global__ void k_fill_i32(int32_t* p, int32_t n, int32_t v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_index_sort(const IndexArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_index_sort, dim3(grid), dim3(kSortThreads), 0, s, a);
     return hipGetLastError();

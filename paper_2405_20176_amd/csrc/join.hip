@@ -124,6 +124,10 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
         int cnt = 0;
         double sum = 0.0;
         float thr = KC > 0 ? fmaxf(kd[KS - 1], eps2) : eps2;
+        // work counters (wavefront-uniform)
+        const int nq = min(kTile, n - t0 * kTile);
+        long long pairs = 0;
+        int scanned = 0, skipped = 0;
 
         for (int s = wave; s < nt; s += S) {
             const int t = spiral(t0, s, nt);
@@ -135,8 +139,13 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
                     const float g = fmaxf(fmaxf(bx[f] - q[f], q[f] - bx[DP + f]), 0.f);
                     lb = fmaf(g, g, lb);
                 }
-                if (!__any(lb <= thr)) continue;
+                if (!__any(lb <= thr)) {
+                    ++skipped;
+                    continue;
+                }
             }
+            ++scanned;
+            pairs += (long long)nq * min(kTile, n - t * kTile);
             const int cbase = t * kTile;
 #pragma unroll 1
             for (int g = 0; g < kTile; g += 4) {
@@ -172,6 +181,13 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
                     }
                 }
             }
+        }
+
+        if (A.stats && lane == 0) {
+            atomicAdd(A.stats + 0, (unsigned long long)pairs);
+            atomicAdd(A.stats + 1, (unsigned long long)scanned);
+            atomicAdd(A.stats + 2, (unsigned long long)skipped);
+            atomicAdd(A.stats + 3, (unsigned long long)pairs * D);
         }
 
         // Merge the split wavefronts' partial results into wavefront 0.

@@ -72,6 +72,7 @@ struct JoinArgs {
     int32_t total_units;
     int32_t* counter;
     int32_t split;               // waves per workgroup sharing a query tile
+    unsigned long long* stats;   // optional [4] counters (see snaps_tuning.stats)
 };
 
 struct RankArgs {
@@ -83,6 +84,7 @@ struct RankArgs {
 hipError_t launch_index_sort(const IndexArgs& a, int grid, hipStream_t s);
 hipError_t launch_reorder(const Meta& m, int32_t n_jobs, int32_t total_tiles, hipStream_t s);
 hipError_t launch_rank(const RankArgs& a, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t n, int32_t v, hipStream_t s);
 // Join kernel for dimensionality D, top-k capacity class kc and filter
 // flavour xf; grid == 0 asks for a persistent grid filling the device.
 hipError_t launch_join(int D, int kc, int xf, const JoinArgs& a, int grid, hipStream_t s);
