@@ -45,8 +45,10 @@
  *             message for the last non-OK return of the calling thread.
  *   Numerics: distances are evaluated in float32 in the direct form
  *             sum_f (x_f - y_f)^2; eps sums are accumulated in float64.
- *   Limits:   n <= 32768 objects per job in this version (larger n returns
- *             SNAPS_EUNSUPPORTED); 1 <= k <= min(32, n - 1).
+ *   Limits:   2 <= n <= 2^30 objects per job (larger n returns
+ *             SNAPS_EUNSUPPORTED); 1 <= k <= min(32, n - 1).  Jobs with
+ *             n <= 32768 are indexed and ranked inside one workgroup's LDS,
+ *             larger ones through a device-wide radix sort.
  */
 #ifndef SNAPS_H
 #define SNAPS_H
@@ -133,8 +135,10 @@ const char* snaps_version(void);
 
 /* Workspace bytes needed by one call of the given operation on one job of n
  * objects in a d-dimensional subspace with k neighbours (k is ignored by
- * SNAPS_OP_EPS and SNAPS_OP_RANK, d by SNAPS_OP_RANK).  Returns 0 for
- * invalid arguments.  Pure host function. */
+ * SNAPS_OP_EPS and SNAPS_OP_RANK, d by SNAPS_OP_RANK).  SNAPS_OP_SCORES
+ * includes the scratch of the rank pass.  Returns 0 for invalid arguments
+ * (and for SNAPS_OP_RANK with n <= 32768, which needs no workspace).  Pure
+ * host function. */
 size_t snaps_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t k);
 
 /* Workspace bytes needed by snaps_outlier_scores for this list of jobs.
@@ -180,7 +184,9 @@ int snaps_outlier_scores(const snaps_job* jobs, int32_t n_jobs, const snaps_tuni
  * eps_mean whatever their stored mean.
  *   rank  [4][n] int32 device, output, rows in the order
  *         (eps_count, eps_mean, indeg, knn_mean)
- * eps_count and indeg values must lie in [0, n). */
+ *   ws    workspace of snaps_workspace_bytes(SNAPS_OP_RANK, n, 0, 0) bytes
+ *         (none needed for n <= 32768; NULL then allowed)
+ * eps_count and indeg values must be non-negative. */
 int snaps_rank(const int32_t* eps_count, const float* eps_mean, const int32_t* indeg,
                const float* knn_mean, int64_t n, int32_t* rank,
                void* ws, size_t ws_bytes, void* stream);

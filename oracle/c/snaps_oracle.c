@@ -47,15 +47,18 @@ int oracle_num_threads(void) {
  * band     int32 [m]      number of other objects with band_lo <= D <= band_hi
  *                         (NULL to skip); tests use it to find objects that
  *                         have a neighbour within rounding distance of eps
+ * qids     int64 [m]      with q == NULL: the self-join is evaluated only for
+ *                         these object ids (row t of the outputs is object
+ *                         qids[t]); NULL means every object
  * k may be 0 (no kNN), eps may be negative (no range join).
  */
 int oracle_join(const float* x, int64_t n, int32_t d, const float* q, int64_t m,
                 int32_t k, double eps, int32_t* ids, double* dist, double* next,
                 int32_t* cnt, double* sum, int32_t* band, double band_lo, double band_hi,
-                int32_t nthreads) {
+                const int64_t* qids, int32_t nthreads) {
     if (n < 1 || d < 1 || k < 0 || k > 64) return -1;
     const int self = (q == 0);
-    if (self) { q = x; m = n; }
+    if (self) { q = x; if (!qids) m = n; }
     if (self && k > n - 1) return -1;
     if (!self && k > n) return -1;
 #ifdef _OPENMP
@@ -64,7 +67,8 @@ int oracle_join(const float* x, int64_t n, int32_t d, const float* q, int64_t m,
     (void)nthreads;
 #endif
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t i = 0; i < m; ++i) {
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t i = (self && qids) ? qids[t] : t;   /* object (self) or query row */
         double bd[65];
         int64_t bj[65];
         int kk = k + 1;              /* keep one extra to report the next distance */
@@ -94,14 +98,14 @@ int oracle_join(const float* x, int64_t n, int32_t d, const float* q, int64_t m,
                 bj[p] = j;
             }
         }
-        for (int t = 0; t < k; ++t) {
-            ids[i * k + t] = (int32_t)bj[t];
-            dist[i * k + t] = bd[t];
+        for (int u = 0; u < k; ++u) {
+            ids[t * k + u] = (int32_t)bj[u];
+            dist[t * k + u] = bd[u];
         }
-        if (next) next[i] = (k > 0) ? bd[k] : INFINITY;
-        if (cnt) cnt[i] = c;
-        if (sum) sum[i] = s;
-        if (band) band[i] = bc;
+        if (next) next[t] = (k > 0) ? bd[k] : INFINITY;
+        if (cnt) cnt[t] = c;
+        if (sum) sum[t] = s;
+        if (band) band[t] = bc;
     }
     return 0;
 }

@@ -42,7 +42,7 @@ def _load():
             ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
             ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
-            ctypes.c_int32]
+            ctypes.c_void_p, ctypes.c_int32]
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -52,17 +52,22 @@ def num_threads() -> int:
     return int(_load().oracle_num_threads())
 
 
-def join(X, k: int, eps: float, queries=None, nthreads: int = 0, band=None):
+def join(X, k: int, eps: float, queries=None, nthreads: int = 0, band=None, qids=None):
     """Raw join results for a projected population ``X`` [n, d] (float32
     values).  Returns dict(knn_ids, knn_dist, knn_next, eps_count, eps_sum)
     and, when ``band=(lo, hi)`` is given, ``band``: the number of other
-    objects at a distance in [lo, hi]."""
+    objects at a distance in [lo, hi].  ``qids`` restricts the self-join to
+    those object ids (rows of the result follow ``qids``)."""
     lib = _load()
     x = np.ascontiguousarray(X, dtype=np.float32)
     n, d = x.shape
+    qid_arr = None
     if queries is None:
         qp, m = None, n
         q = None
+        if qids is not None:
+            qid_arr = np.ascontiguousarray(qids, dtype=np.int64)
+            m = qid_arr.size
     else:
         q = np.ascontiguousarray(queries, dtype=np.float32)
         m = q.shape[0]
@@ -78,7 +83,7 @@ def join(X, k: int, eps: float, queries=None, nthreads: int = 0, band=None):
     rc = lib.oracle_join(x.ctypes.data, n, d, qp, m, k, float(eps), ids.ctypes.data,
                          dist.ctypes.data, nxt.ctypes.data, cnt.ctypes.data, ssum.ctypes.data,
                          bnd.ctypes.data if band is not None else None, float(blo), float(bhi),
-                         int(nthreads))
+                         qid_arr.ctypes.data if qid_arr is not None else None, int(nthreads))
     if rc != 0:
         raise ValueError("oracle_join rejected its arguments")
     out = dict(knn_ids=ids[:, :k].astype(np.int64), knn_dist=dist[:, :k], knn_next=nxt,

@@ -39,6 +39,7 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 constexpr size_t kAlign = 256;
+constexpr int64_t kMaxN = int64_t(1) << 30;   // objects per job (ids and tile counts stay in int32)
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 int popcount32(uint32_t m) { return __builtin_popcount(m); }
@@ -60,9 +61,9 @@ int check_population(const snaps_population* P, uint32_t mask) {
         return fail(SNAPS_EINVAL, "mask 0x%x names features beyond n_features = %d", mask, P->n_features);
     const int d = popcount32(mask);
     if (d < 2 || d > kMaxD) return fail(SNAPS_EINVAL, "subspace needs 2..%d features (mask 0x%x has %d)", kMaxD, mask, d);
-    if (P->n > kLdsSortMax)
-        return fail(SNAPS_EUNSUPPORTED, "n = %lld objects exceeds this version's limit of %d per job",
-                    (long long)P->n, kLdsSortMax);
+    if (P->n > kMaxN)
+        return fail(SNAPS_EUNSUPPORTED, "n = %lld objects exceeds this version's limit of %lld per job",
+                    (long long)P->n, (long long)kMaxN);
     return SNAPS_OK;
 }
 
@@ -116,26 +117,54 @@ int device_info(DeviceInfo* out) {
 
 // What one job needs, decided on the host.
 struct JobPlan {
-    int32_t n, d, k, kc, ntiles;
-    size_t xs_off, perm_off, box_off, bytes;
+    int32_t n, d, k, kc, ntiles, nchunks;
+    bool large;              // index and ranks through the device-wide radix sort
+    bool rank;               // rank scratch reserved
+    size_t xs_off, perm_off, box_off;
+    size_t ihist_off, acc_off, sel_off;          // large index scratch
+    size_t rkey_off, rpong_off, rhist_off, rnd_off;  // large rank scratch
+    size_t bytes;
 };
 
-JobPlan plan_job(int64_t n, int d, int k) {
+JobPlan plan_job(int64_t n, int d, int k, bool with_rank) {
     JobPlan p{};
     p.n = (int32_t)n;
     p.d = d;
     p.k = k;
     p.kc = kc_class(k);
     p.ntiles = (int32_t)((n + kTile - 1) / kTile);
+    p.nchunks = (int32_t)((n + kRadixChunk - 1) / kRadixChunk);
+    p.large = n > kLdsSortMax;
+    p.rank = with_rank;
     const size_t rows = (size_t)p.ntiles * kTile;
     const int dp = row_stride(d);
     size_t off = 0;
+    // xs also hosts the large-index sort keys (3 x rows words <= rows x dp
+    // floats) before the reorder overwrites it with coordinates.
     p.xs_off = off;
     off += align_up(rows * dp * sizeof(float));
     p.perm_off = off;
     off += align_up(rows * sizeof(int32_t));
     p.box_off = off;
     off += align_up((size_t)p.ntiles * 2 * dp * sizeof(float));
+    if (p.large) {
+        p.ihist_off = off;
+        off += align_up((size_t)256 * p.nchunks * sizeof(int32_t));
+        p.acc_off = off;
+        off += align_up(2 * kMaxD * sizeof(double));
+        p.sel_off = off;
+        off += align_up(3 * kMaxIndexDims * sizeof(float));
+        if (with_rank) {
+            p.rkey_off = off;
+            off += align_up(4 * rows * sizeof(uint32_t));
+            p.rpong_off = off;
+            off += align_up(4 * rows * sizeof(uint32_t));
+            p.rhist_off = off;
+            off += align_up((size_t)4 * 256 * p.nchunks * sizeof(int32_t));
+            p.rnd_off = off;
+            off += align_up(4 * sizeof(int32_t));
+        }
+    }
     p.bytes = off;
     return p;
 }
@@ -147,22 +176,31 @@ int class_id(int d, int kc) {
 }
 
 struct MetaLayout {
-    size_t table, order, unit_prefix, tile_prefix, counters, bytes;
+    size_t table, order, unit_prefix, tile_prefix, counters;
+    size_t li, iseg, ichunk, lr, rseg, rchunk, rsegchunk;
+    size_t bytes;
 };
 
-MetaLayout meta_layout(int n_jobs) {
+MetaLayout meta_layout(int n_jobs, int n_large, int n_lrank) {
     MetaLayout m{};
     size_t off = 0;
-    m.table = off;
-    off += align_up((size_t)n_jobs * sizeof(DevJob));
-    m.order = off;
-    off += align_up((size_t)n_jobs * sizeof(int32_t));
-    m.unit_prefix = off;
-    off += align_up((size_t)(n_jobs + kNumClasses) * sizeof(int32_t));
-    m.tile_prefix = off;
-    off += align_up((size_t)(n_jobs + 1) * sizeof(int32_t));
-    m.counters = off;
-    off += align_up((size_t)kNumClasses * sizeof(int32_t));
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    m.table = take((size_t)n_jobs * sizeof(DevJob));
+    m.order = take((size_t)n_jobs * sizeof(int32_t));
+    m.unit_prefix = take((size_t)(n_jobs + kNumClasses) * sizeof(int32_t));
+    m.tile_prefix = take((size_t)(n_jobs + 1) * sizeof(int32_t));
+    m.counters = take((size_t)kNumClasses * sizeof(int32_t));
+    m.li = take((size_t)n_large * sizeof(LargeIndex));
+    m.iseg = take((size_t)n_large * sizeof(SortSeg));
+    m.ichunk = take((size_t)(n_large + 1) * sizeof(int32_t));
+    m.lr = take((size_t)n_lrank * sizeof(LargeRank));
+    m.rseg = take((size_t)4 * n_lrank * sizeof(SortSeg));
+    m.rchunk = take((size_t)(n_lrank + 1) * sizeof(int32_t));
+    m.rsegchunk = take((size_t)(4 * n_lrank + 1) * sizeof(int32_t));
     m.bytes = off;
     return m;
 }
@@ -202,9 +240,14 @@ DevJob make_devjob(const snaps_population* P, uint32_t mask, const JobPlan& p, f
     int f = 0;
     for (int b = 0; b < 32; ++b)
         if ((mask >> b) & 1u) j.feat[f++] = b;
-    j.idbits = std::max(1, ceil_log2(p.n));
-    j.bits = std::max(1, (32 - j.idbits) / c);
-    if (j.bits * c > 32 - j.idbits) j.bits = (32 - j.idbits) / c;
+    if (p.large) {
+        // keys are sorted with the id as a separate payload: all 32 bits
+        j.idbits = 0;
+        j.bits = 32 / c;
+    } else {
+        j.idbits = std::max(1, ceil_log2(p.n));
+        j.bits = std::max(1, (32 - j.idbits) / c);
+    }
     if (tn.mode == 1) j.prune = 0;
     else if (tn.mode == 2) j.prune = 1;
     else j.prune = p.d <= 10 ? 1 : 0;
@@ -214,12 +257,18 @@ DevJob make_devjob(const snaps_population* P, uint32_t mask, const JobPlan& p, f
     return j;
 }
 
-int choose_split(const Tune& tn, int64_t total_units, int cus) {
-    if (tn.split > 0) return tn.split;
-    // Aim for about eight wavefronts per SIMD (four SIMDs per CU).
-    const int64_t target = (int64_t)cus * 4 * 8;
+constexpr size_t kMaxJoinLds = 120 * 1024;
+
+int choose_split(const Tune& tn, int64_t total_units, int cus, int kc) {
     int s = 1;
-    while (s < 8 && total_units * s < target) s <<= 1;
+    if (tn.split > 0) {
+        s = tn.split;
+    } else {
+        // Aim for about eight wavefronts per SIMD (four SIMDs per CU).
+        const int64_t target = (int64_t)cus * 4 * 8;
+        while (s < 8 && total_units * s < target) s <<= 1;
+    }
+    while (s > 1 && join_lds_bytes(kc, s) > kMaxJoinLds) s >>= 1;
     return s;
 }
 
@@ -230,8 +279,7 @@ int launch_joins(const Meta& meta, const std::vector<int>& class_of_slot, const 
     (void)class_of_slot;
     int64_t all_units = 0;
     for (int c = 0; c < kNumClasses; ++c) all_units += cls_units[c];
-    const int split = choose_split(tn, all_units, cus);
-    const int xf = 0;
+    const int xf = tn.filter == 1 ? 0 : 1;
     hipError_t fe = launch_fill_i32(meta.counters, meta.n_counters, 0, s);
     if (fe != hipSuccess) return hip_fail(fe, "counter reset");
     for (int c = 0; c < kNumClasses; ++c) {
@@ -239,6 +287,7 @@ int launch_joins(const Meta& meta, const std::vector<int>& class_of_slot, const 
         const int d = c / 5;
         static const int kKc[5] = {0, 5, 10, 20, 32};
         const int kc = kKc[c % 5];
+        const int split = choose_split(tn, all_units, cus, kc);
         JoinArgs a{};
         a.table = meta.table;
         a.order = meta.order + cls_order_off[c];
@@ -272,8 +321,21 @@ struct RunJob {
     float* knn_dist;
 };
 
+void count_large(const std::vector<RunJob>& jobs, int* n_large, int* n_lrank) {
+    *n_large = 0;
+    *n_lrank = 0;
+    for (const auto& j : jobs) {
+        if (j.plan.large) {
+            ++*n_large;
+            if (j.rank) ++*n_lrank;
+        }
+    }
+}
+
 size_t run_workspace(const std::vector<RunJob>& jobs) {
-    size_t b = meta_layout((int)jobs.size()).bytes;
+    int nl = 0, nr = 0;
+    count_large(jobs, &nl, &nr);
+    size_t b = meta_layout((int)jobs.size(), nl, nr).bytes;
     for (const auto& j : jobs) b += j.plan.bytes;
     return b;
 }
@@ -291,9 +353,11 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
     DeviceInfo di;
     int rc = device_info(&di);
     if (rc != SNAPS_OK) return rc;
+    int n_large = 0, n_lrank = 0;
+    count_large(jobs, &n_large, &n_lrank);
 
     char* base = static_cast<char*>(ws);
-    const MetaLayout ml = meta_layout(n_jobs);
+    const MetaLayout ml = meta_layout(n_jobs, n_large, n_lrank);
     Meta meta{};
     meta.table = reinterpret_cast<DevJob*>(base + ml.table);
     meta.order = reinterpret_cast<int32_t*>(base + ml.order);
@@ -303,11 +367,13 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
     meta.n_counters = kNumClasses;
 
     std::vector<DevJob> table(n_jobs);
+    std::vector<char*> job_base(n_jobs);
     size_t off = ml.bytes;
     int64_t total_tiles = 0;
     std::vector<int32_t> tile_prefix(n_jobs + 1, 0);
     for (int i = 0; i < n_jobs; ++i) {
         const RunJob& r = jobs[i];
+        job_base[i] = base + off;
         DevJob j = make_devjob(r.pop, r.mask, r.plan, r.eps, tn, base + off);
         j.eps_count = r.eps_count;
         j.eps_mean = r.eps_mean;
@@ -319,9 +385,9 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         table[i] = j;
         off += r.plan.bytes;
         total_tiles += r.plan.ntiles;
+        if (total_tiles > INT32_MAX / 2) return fail(SNAPS_EUNSUPPORTED, "too many tiles in one call");
         tile_prefix[i + 1] = (int32_t)total_tiles;
     }
-    if (total_tiles > INT32_MAX / 2) return fail(SNAPS_EUNSUPPORTED, "too many tiles in one call");
 
     // Group jobs into kernel classes (dimensionality, top-k capacity); within
     // a class, the most expensive jobs (largest n) go first.
@@ -341,55 +407,130 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         cls_prefix_off[c] = (int)unit_prefix.size();
         int64_t acc = 0;
         unit_prefix.push_back(0);
+        const int ql = join_ql(c % 5 == 0 ? 0 : (c % 5 == 4 ? 32 : 5));
         for (int i : m) {
             order.push_back(i);
-            acc += jobs[i].plan.ntiles;
+            acc += (jobs[i].plan.ntiles + ql - 1) / ql;
             unit_prefix.push_back((int32_t)acc);
         }
         cls_units[c] = (int)acc;
+    }
+
+    // Device-wide sort descriptors of the large jobs.
+    std::vector<LargeIndex> lidx;
+    std::vector<SortSeg> iseg;
+    std::vector<int32_t> ichunk(1, 0);
+    std::vector<LargeRank> lrank;
+    std::vector<SortSeg> rseg;
+    std::vector<int32_t> rchunk(1, 0), rsegchunk(1, 0);
+    int32_t* rank_nd_base = nullptr;
+    (void)rank_nd_base;
+    for (int i = 0; i < n_jobs; ++i) {
+        const JobPlan& p = jobs[i].plan;
+        if (!p.large) continue;
+        char* jb = job_base[i];
+        const size_t rows = (size_t)p.ntiles * kTile;
+        uint32_t* xs_words = reinterpret_cast<uint32_t*>(jb + p.xs_off);
+        LargeIndex L{};
+        L.job = i;
+        L.nchunks = p.nchunks;
+        L.acc = reinterpret_cast<double*>(jb + p.acc_off);
+        L.sel_col = reinterpret_cast<int32_t*>(jb + p.sel_off);
+        L.sel_lo = reinterpret_cast<float*>(jb + p.sel_off) + kMaxIndexDims;
+        L.sel_scale = reinterpret_cast<float*>(jb + p.sel_off) + 2 * kMaxIndexDims;
+        L.keys = xs_words;
+        L.vals = reinterpret_cast<uint32_t*>(table[i].perm);
+        lidx.push_back(L);
+        SortSeg g{};
+        g.key[0] = xs_words;
+        g.key[1] = xs_words + rows;
+        g.val[0] = L.vals;
+        g.val[1] = xs_words + 2 * rows;
+        g.hist = reinterpret_cast<int32_t*>(jb + p.ihist_off);
+        g.n = p.n;
+        g.nchunks = p.nchunks;
+        iseg.push_back(g);
+        ichunk.push_back(ichunk.back() + p.nchunks);
+        if (jobs[i].rank) {
+            LargeRank R{};
+            R.job = i;
+            R.nchunks = p.nchunks;
+            R.n_distinct = reinterpret_cast<int32_t*>(jb + p.rnd_off);
+            for (int m = 0; m < 4; ++m) {
+                R.keys[m] = reinterpret_cast<uint32_t*>(jb + p.rkey_off) + m * rows;
+                R.distinct[m] = reinterpret_cast<uint32_t*>(jb + p.rpong_off) + m * rows;
+                SortSeg rg{};
+                rg.key[0] = R.keys[m];
+                rg.key[1] = R.distinct[m];
+                rg.val[0] = rg.val[1] = nullptr;
+                rg.hist = reinterpret_cast<int32_t*>(jb + p.rhist_off) + (size_t)m * 256 * p.nchunks;
+                rg.n = p.n;
+                rg.nchunks = p.nchunks;
+                rseg.push_back(rg);
+                rsegchunk.push_back(rsegchunk.back() + p.nchunks);
+            }
+            lrank.push_back(R);
+            rchunk.push_back(rchunk.back() + p.nchunks);
+        }
     }
 
     hipError_t e;
     const bool do_index = (tn.passes & SNAPS_PASS_INDEX) != 0;
     const bool do_join = (tn.passes & SNAPS_PASS_JOIN) != 0;
     const bool do_rank = (tn.passes & SNAPS_PASS_RANK) != 0;
-    if (n_jobs == 1 && !do_index) {
-        // metadata of a single job is written by the index pass; later passes reuse it
-    } else if (n_jobs == 1) {
-        IndexArgs ia{};
-        ia.meta = meta;
-        ia.n_jobs = 1;
-        ia.seed = 1;
-        ia.single_units = table[0].ntiles;
-        ia.single = table[0];
-        // the single job's class arrays start at offset 0 of order / unit_prefix
-        const int c = class_id(jobs[0].plan.d, jobs[0].plan.kc);
+    const bool seed_single = (n_jobs == 1 && n_large == 0);
+    if (seed_single) {
+        // The metadata of a single small job is written by its index kernel
+        // from kernel arguments (no host-to-device copy); later passes of the
+        // same job reuse it.
         cls_order_off.assign(kNumClasses, 0);
         cls_prefix_off.assign(kNumClasses, 0);
-        (void)c;
-        e = launch_index_sort(ia, 1, s);
-        if (e != hipSuccess) return hip_fail(e, "index sort launch");
+        if (do_index) {
+            IndexArgs ia{};
+            ia.meta = meta;
+            ia.n_jobs = 1;
+            ia.seed = 1;
+            ia.single_units = unit_prefix.back();
+            ia.single_tiles = table[0].ntiles;
+            ia.single = table[0];
+            e = launch_index_sort(ia, 1, s);
+            if (e != hipSuccess) return hip_fail(e, "index sort launch");
+        }
     } else {
         // One host-to-device copy of the metadata block (synchronous for
         // pageable host memory, so the staging buffer can be reused).
         auto& st = staging();
         st.assign(ml.bytes, 0);
-        std::memcpy(st.data() + ml.table, table.data(), table.size() * sizeof(DevJob));
-        std::memcpy(st.data() + ml.order, order.data(), order.size() * sizeof(int32_t));
-        std::memcpy(st.data() + ml.unit_prefix, unit_prefix.data(), unit_prefix.size() * sizeof(int32_t));
-        std::memcpy(st.data() + ml.tile_prefix, tile_prefix.data(), tile_prefix.size() * sizeof(int32_t));
+        auto put = [&](size_t at, const void* src, size_t bytes) {
+            if (bytes) std::memcpy(st.data() + at, src, bytes);
+        };
+        put(ml.table, table.data(), table.size() * sizeof(DevJob));
+        put(ml.order, order.data(), order.size() * sizeof(int32_t));
+        put(ml.unit_prefix, unit_prefix.data(), unit_prefix.size() * sizeof(int32_t));
+        put(ml.tile_prefix, tile_prefix.data(), tile_prefix.size() * sizeof(int32_t));
+        put(ml.li, lidx.data(), lidx.size() * sizeof(LargeIndex));
+        put(ml.iseg, iseg.data(), iseg.size() * sizeof(SortSeg));
+        put(ml.ichunk, ichunk.data(), ichunk.size() * sizeof(int32_t));
+        put(ml.lr, lrank.data(), lrank.size() * sizeof(LargeRank));
+        put(ml.rseg, rseg.data(), rseg.size() * sizeof(SortSeg));
+        put(ml.rchunk, rchunk.data(), rchunk.size() * sizeof(int32_t));
+        put(ml.rsegchunk, rsegchunk.data(), rsegchunk.size() * sizeof(int32_t));
         e = hipMemcpyAsync(base, st.data(), ml.bytes, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "job table upload");
-    }
-    if (do_index) {
-        if (n_jobs > 1) {
+        if (do_index) {
             IndexArgs ia{};
             ia.meta = meta;
             ia.n_jobs = n_jobs;
             ia.seed = 0;
             e = launch_index_sort(ia, n_jobs, s);
             if (e != hipSuccess) return hip_fail(e, "index sort launch");
+            e = launch_large_index(meta.table, reinterpret_cast<const LargeIndex*>(base + ml.li), n_large,
+                                   reinterpret_cast<const int32_t*>(base + ml.ichunk), ichunk.back(),
+                                   reinterpret_cast<const SortSeg*>(base + ml.iseg), s);
+            if (e != hipSuccess) return hip_fail(e, "large index launch");
         }
+    }
+    if (do_index) {
         e = launch_reorder(meta, n_jobs, (int32_t)total_tiles, s);
         if (e != hipSuccess) return hip_fail(e, "reorder launch");
     }
@@ -403,8 +544,23 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         RankArgs ra{meta.table, n_jobs};
         e = launch_rank(ra, s);
         if (e != hipSuccess) return hip_fail(e, "rank launch");
+        e = launch_large_rank(meta.table, reinterpret_cast<const LargeRank*>(base + ml.lr), n_lrank,
+                              reinterpret_cast<const int32_t*>(base + ml.rchunk), rchunk.back(),
+                              reinterpret_cast<const SortSeg*>(base + ml.rseg),
+                              reinterpret_cast<const int32_t*>(base + ml.rsegchunk), rsegchunk.back(), s);
+        if (e != hipSuccess) return hip_fail(e, "large rank launch");
     }
     return SNAPS_OK;
+}
+
+// Workspace of snaps_rank: none for n within one workgroup's LDS, else the
+// metadata block plus key, ping-pong and histogram buffers of 4 segments.
+size_t rank_workspace(int64_t n) {
+    if (n <= kLdsSortMax) return 0;
+    const int64_t nchunks = (n + kRadixChunk - 1) / kRadixChunk;
+    const size_t rows = (size_t)((n + kTile - 1) / kTile) * kTile;
+    return meta_layout(1, 0, 1).bytes + align_up(8 * rows * sizeof(uint32_t)) +
+           align_up((size_t)4 * 256 * nchunks * sizeof(int32_t) + 4 * sizeof(int32_t));
 }
 
 }  // namespace
@@ -416,13 +572,14 @@ const char* snaps_last_error(void) { return g_error.c_str(); }
 const char* snaps_version(void) { return "snaps-mi355x 0.1 (gfx950)"; }
 
 size_t snaps_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t k) {
-    if (n < 2 || n > kLdsSortMax) return 0;
-    if (op == SNAPS_OP_RANK) return 0;
+    if (n < 2 || n > kMaxN) return 0;
+    if (op == SNAPS_OP_RANK) return rank_workspace(n);
     if (d < 2 || d > kMaxD) return 0;
     if (op == SNAPS_OP_EPS) k = 0;
     else if (k < 1 || k > n - 1 || k > kMaxK) return 0;
     if (op != SNAPS_OP_KNN && op != SNAPS_OP_EPS && op != SNAPS_OP_SCORES) return 0;
-    return meta_layout(1).bytes + plan_job(n, d, k).bytes;
+    const JobPlan p = plan_job(n, d, k, op == SNAPS_OP_SCORES);
+    return meta_layout(1, p.large ? 1 : 0, (p.large && op == SNAPS_OP_SCORES) ? 1 : 0).bytes + p.bytes;
 }
 
 static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, std::vector<RunJob>* out) {
@@ -444,7 +601,7 @@ static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, std::vector<RunJo
         r.pop = j.pop;
         r.mask = j.mask;
         r.eps = j.eps;
-        r.plan = plan_job(j.pop->n, popcount32(j.mask), j.k);
+        r.plan = plan_job(j.pop->n, popcount32(j.mask), j.k, j.rank != nullptr);
         r.eps_count = j.out.eps_count;
         r.eps_mean = j.out.eps_mean;
         r.indeg = j.out.indeg;
@@ -473,7 +630,7 @@ int snaps_knn_selfjoin(const snaps_population* P, uint32_t mask, int32_t k, int3
     r.pop = P;
     r.mask = mask;
     r.eps = 0.f;
-    r.plan = plan_job(P->n, popcount32(mask), k);
+    r.plan = plan_job(P->n, popcount32(mask), k, false);
     r.knn_ids = ids;
     r.knn_dist = dist;
     return run({r}, Tune{0, 0, 0, 0}, ws, ws_bytes, static_cast<hipStream_t>(stream));
@@ -494,7 +651,7 @@ int snaps_eps_selfjoin(const snaps_population* P, uint32_t mask, float eps, int3
     r.pop = P;
     r.mask = mask;
     r.eps = eps;
-    r.plan = plan_job(P->n, popcount32(mask), 0);
+    r.plan = plan_job(P->n, popcount32(mask), 0, false);
     r.eps_count = count;
     r.eps_mean = mean_dist;
     return run({r}, Tune{0, 0, 0, 0}, ws, ws_bytes, static_cast<hipStream_t>(stream));
@@ -512,12 +669,11 @@ int snaps_outlier_scores(const snaps_job* jobs, int32_t n_jobs, const snaps_tuni
 
 int snaps_rank(const int32_t* eps_count, const float* eps_mean, const int32_t* indeg, const float* knn_mean,
                int64_t n, int32_t* rank, void* ws, size_t ws_bytes, void* stream) {
-    (void)ws;
-    (void)ws_bytes;
     if (!eps_count || !eps_mean || !indeg || !knn_mean || !rank)
         return fail(SNAPS_EINVAL, "every metric array and the rank output are required");
     if (n < 1) return fail(SNAPS_EINVAL, "n must be >= 1");
-    if (n > kLdsSortMax) return fail(SNAPS_EUNSUPPORTED, "n = %lld exceeds this version's limit of %d", (long long)n, kLdsSortMax);
+    if (n > kMaxN) return fail(SNAPS_EUNSUPPORTED, "n = %lld exceeds this version's limit", (long long)n);
+    hipStream_t s = static_cast<hipStream_t>(stream);
     DevJob j;
     std::memset(&j, 0, sizeof(j));
     j.n = (int32_t)n;
@@ -526,8 +682,55 @@ int snaps_rank(const int32_t* eps_count, const float* eps_mean, const int32_t* i
     j.indeg = const_cast<int32_t*>(indeg);
     j.knn_mean = const_cast<float*>(knn_mean);
     j.rank = rank;
-    hipError_t e = launch_rank_single(j, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return hip_fail(e, "rank launch");
+    if (n <= kLdsSortMax) {
+        hipError_t e = launch_rank_single(j, s);
+        if (e != hipSuccess) return hip_fail(e, "rank launch");
+        return SNAPS_OK;
+    }
+    const size_t need = rank_workspace(n);
+    if (!ws) return fail(SNAPS_EINVAL, "workspace is NULL (%zu bytes needed)", need);
+    if (ws_bytes < need) return fail(SNAPS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    char* base = static_cast<char*>(ws);
+    const MetaLayout ml = meta_layout(1, 0, 1);
+    const int nchunks = (int)((n + kRadixChunk - 1) / kRadixChunk);
+    const size_t rows = (size_t)((n + kTile - 1) / kTile) * kTile;
+    char* jb = base + ml.bytes;
+    uint32_t* keys = reinterpret_cast<uint32_t*>(jb);
+    uint32_t* pong = keys + 4 * rows;
+    int32_t* hist = reinterpret_cast<int32_t*>(jb + align_up(8 * rows * sizeof(uint32_t)));
+    int32_t* nd = hist + (size_t)4 * 256 * nchunks;
+    LargeRank R{};
+    R.job = 0;
+    R.nchunks = nchunks;
+    R.n_distinct = nd;
+    std::vector<SortSeg> segs(4);
+    std::vector<int32_t> segchunk(5, 0);
+    for (int m = 0; m < 4; ++m) {
+        R.keys[m] = keys + m * rows;
+        R.distinct[m] = pong + m * rows;
+        SortSeg& g = segs[m];
+        g.key[0] = R.keys[m];
+        g.key[1] = R.distinct[m];
+        g.hist = hist + (size_t)m * 256 * nchunks;
+        g.n = n;
+        g.nchunks = nchunks;
+        segchunk[m + 1] = segchunk[m] + nchunks;
+    }
+    const int32_t chunk[2] = {0, nchunks};
+    auto& st = staging();
+    st.assign(ml.bytes, 0);
+    std::memcpy(st.data() + ml.table, &j, sizeof(DevJob));
+    std::memcpy(st.data() + ml.lr, &R, sizeof(LargeRank));
+    std::memcpy(st.data() + ml.rseg, segs.data(), 4 * sizeof(SortSeg));
+    std::memcpy(st.data() + ml.rchunk, chunk, sizeof(chunk));
+    std::memcpy(st.data() + ml.rsegchunk, segchunk.data(), 5 * sizeof(int32_t));
+    hipError_t e = hipMemcpyAsync(base, st.data(), ml.bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "rank table upload");
+    e = launch_large_rank(reinterpret_cast<const DevJob*>(base + ml.table), reinterpret_cast<const LargeRank*>(base + ml.lr),
+                          1, reinterpret_cast<const int32_t*>(base + ml.rchunk), nchunks,
+                          reinterpret_cast<const SortSeg*>(base + ml.rseg),
+                          reinterpret_cast<const int32_t*>(base + ml.rsegchunk), 4 * nchunks, s);
+    if (e != hipSuccess) return hip_fail(e, "large rank launch");
     return SNAPS_OK;
 }
 

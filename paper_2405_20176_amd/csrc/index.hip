@@ -10,7 +10,7 @@
 //      permutation `perm`.
 //   2. k_reorder (one wavefront per tile of 64 positions): gathers the d
 //      subspace columns of every object in sorted order into a row-major
-//      array (plus the squared norm), pads the last tile with NaN rows, and
+//      array (plus a scaled squared norm), pads the last tile with NaN rows, and
 //      records each tile's bounding box in all d dimensions.
 //
 // Any order of the objects gives the same join results (the join prunes a
@@ -18,6 +18,7 @@
 // decides how much the join can skip.
 #include "snaps_internal.h"
 #include "common.cuh"
+#include "keys.cuh"
 
 #include <climits>
 
@@ -39,12 +40,13 @@ __global__ __launch_bounds__(kSortThreads) void k_index_sort(IndexArgs A) {
             A.meta.unit_prefix[0] = 0;
             A.meta.unit_prefix[1] = A.single_units;
             A.meta.tile_prefix[0] = 0;
-            A.meta.tile_prefix[1] = A.single_units;
+            A.meta.tile_prefix[1] = A.single_tiles;
         }
     } else {
         J = A.meta.table[blockIdx.x];
     }
     if (blockIdx.x == 0 && (int)threadIdx.x < A.meta.n_counters) A.meta.counters[threadIdx.x] = 0;
+    if (J.n > kLdsSortMax) return;           // indexed by the device-wide path
 
     const int n = J.n;
     const int d = J.d;
@@ -87,50 +89,14 @@ __global__ __launch_bounds__(kSortThreads) void k_index_sort(IndexArgs A) {
             mean[f] = (float)m;
             sd[f] = var > 0.0 ? (float)sqrt(var) : 0.f;
         }
-        // The c dimensions with the largest spread (lower index on ties).
-        unsigned used = 0;
-        for (int e = 0; e < c; ++e) {
-            int best = -1;
-            for (int f = 0; f < d; ++f) {
-                if ((used >> f) & 1u) continue;
-                if (best < 0 || sd[f] > sd[best]) best = f;
-            }
-            used |= 1u << best;
-            const float sg = sd[best];
-            const float lo = sg > 0.f ? mean[best] - 3.f * sg : mean[best] - 0.5f;
-            const float hi = sg > 0.f ? mean[best] + 3.f * sg : mean[best] + 0.5f;
-            s_col[e] = J.feat[best];
-            s_lo[e] = lo;
-            s_scale[e] = (float)(1u << J.bits) / (hi - lo);
-        }
+        choose_index_dims(J, mean, sd, s_col, s_lo, s_scale);
     }
     __syncthreads();
 
     const int P = next_pow2(n < 2 ? 2 : n);
-    const int bits = J.bits;
-    const uint32_t qmax = (1u << bits) - 1u;
     for (int i = tid; i < P; i += blockDim.x) {
         uint32_t packed = 0xFFFFFFFFu;
-        if (i < n) {
-            uint32_t qv[kMaxIndexDims];
-#pragma unroll
-            for (int e = 0; e < kMaxIndexDims; ++e) {
-                qv[e] = 0;
-                if (e < c) {
-                    const float v = J.cols[(int64_t)s_col[e] * J.ld + i];
-                    float t = (v - s_lo[e]) * s_scale[e];
-                    t = fminf(fmaxf(t, 0.f), (float)qmax);
-                    qv[e] = (uint32_t)t;
-                }
-            }
-            uint32_t key = 0;
-            for (int b = bits - 1; b >= 0; --b) {
-#pragma unroll
-                for (int e = 0; e < kMaxIndexDims; ++e)
-                    if (e < c) key = (key << 1) | ((qv[e] >> b) & 1u);
-            }
-            packed = (key << J.idbits) | (uint32_t)i;
-        }
+        if (i < n) packed = (morton_key(J, s_col, s_lo, s_scale, i) << J.idbits) | (uint32_t)i;
         buf[i] = packed;
     }
     __syncthreads();
@@ -179,7 +145,10 @@ __global__ __launch_bounds__(64) void k_reorder(Meta m, int32_t n_jobs) {
             row[f] = v;
         }
     }
-    row[d] = valid ? norm : qnan;
+    // Slot d: -pn (1 - c0) / 2, the addend of the join's expanded-form
+    // prefilter (c0 = (8d + 24) 2^-24, see the join kernel).
+    const float c0 = (float)(8 * d + 24) * 5.9604644775390625e-8f;
+    row[d] = valid ? -0.5f * (norm * (1.0f - c0)) : qnan;
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t n, int32_t v) {

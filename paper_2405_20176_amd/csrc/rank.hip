@@ -13,27 +13,9 @@
 // (binary search).
 #include "snaps_internal.h"
 #include "common.cuh"
+#include "keys.cuh"
 
 namespace snaps {
-
-namespace {
-
-// Monotone map of a float to an unsigned key (ascending float order).
-__device__ __forceinline__ uint32_t asc_key(float x) {
-    const uint32_t b = __float_as_uint(x);
-    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-
-__device__ __forceinline__ uint32_t metric_key(const DevJob& J, int metric, int i) {
-    switch (metric) {
-        case 0: return (uint32_t)J.eps_count[i];
-        case 1: return ~asc_key(J.eps_count[i] > 0 ? J.eps_mean[i] : INFINITY);
-        case 2: return (uint32_t)J.indeg[i];
-        default: return ~asc_key(J.knn_mean[i]);
-    }
-}
-
-}  // namespace
 
 struct RankLaunch {
     RankArgs a;
@@ -45,7 +27,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rank(RankLaunch L) {
     __shared__ uint32_t buf[kLdsSortMax];
     __shared__ int tmp[17];
     const DevJob J = L.seed ? L.single : L.a.table[blockIdx.x];
-    if (J.rank == nullptr) return;
+    if (J.rank == nullptr || J.n > kLdsSortMax) return;   // large jobs: device-wide path
     const int metric = blockIdx.y;
     const int n = J.n;
     const int tid = threadIdx.x;

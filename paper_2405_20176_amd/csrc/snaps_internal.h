@@ -13,6 +13,7 @@ constexpr int kMaxIndexDims = 6;     // c <= 6 indexed dimensions (paper Sec. 3.
 constexpr int kLdsSortMax = 32768;   // largest n sorted inside one workgroup's LDS
 constexpr int kMaxK = 32;            // largest k
 constexpr int kSortThreads = 1024;
+constexpr int kRadixChunk = 4096;    // elements per workgroup of the device-wide radix sort
 
 // Row stride (floats) of the tile-ordered coordinate array for dimension d:
 // d coordinates, the squared norm, padded to a multiple of 4 floats.
@@ -60,7 +61,8 @@ struct IndexArgs {
     Meta meta;
     int32_t n_jobs;
     int32_t seed;            // 1: single job passed by value, block 0 writes the metadata
-    int32_t single_units;    // tiles of the single job
+    int32_t single_units;    // join work units of the single job
+    int32_t single_tiles;    // tiles of the single job
     DevJob single;
 };
 
@@ -75,16 +77,62 @@ struct JoinArgs {
     unsigned long long* stats;   // optional [4] counters (see snaps_tuning.stats)
 };
 
+// One segment of the device-wide radix sort: ping-pong key (and optional
+// payload) buffers, result in buffer 0 after an even number of passes.
+struct SortSeg {
+    uint32_t* key[2];
+    uint32_t* val[2];        // null: keys only
+    int32_t* hist;           // [256][nchunks] scratch
+    int64_t n;
+    int32_t nchunks;
+    int32_t pad0;
+};
+
+// Index build of a job too large for the LDS sort: statistics accumulators,
+// the chosen index dimensions and the key buffer of its sort segment.
+struct LargeIndex {
+    int32_t job;             // index into the job table
+    int32_t nchunks;
+    double* acc;             // [2][kMaxD] sums and sums of squares
+    int32_t* sel_col;        // [kMaxIndexDims] population columns of the index dims
+    float* sel_lo;           // [kMaxIndexDims]
+    float* sel_scale;        // [kMaxIndexDims]
+    uint32_t* keys;          // [ntiles*64] Morton keys (sort buffer 0)
+    uint32_t* vals;          // [ntiles*64] object ids (sort buffer 0 payload = perm)
+};
+
+// Rank of a job too large for the LDS sort: per metric, the sort segment
+// holding its keys and the number of distinct values found.
+struct LargeRank {
+    int32_t job;
+    int32_t nchunks;
+    uint32_t* keys[4];       // sorted keys of each metric (buffer 0)
+    uint32_t* distinct[4];   // distinct sorted keys (buffer 1 is reused)
+    int32_t* n_distinct;     // [4]
+};
+
 struct RankArgs {
     const DevJob* table;
     int32_t n_jobs;
 };
+
+// Queries per lane of the join instantiation for top-k capacity kc: 2 for
+// capacities up to 20 (register budget), 1 for 32 and for the range-only join.
+__host__ __device__ constexpr int join_ql(int kc) { return kc < 0 ? 2 : 1; }
 
 // Launchers (each returns the HIP status of the launch).
 hipError_t launch_index_sort(const IndexArgs& a, int grid, hipStream_t s);
 hipError_t launch_reorder(const Meta& m, int32_t n_jobs, int32_t total_tiles, hipStream_t s);
 hipError_t launch_rank(const RankArgs& a, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t n, int32_t v, hipStream_t s);
+hipError_t launch_radix_sort(const SortSeg* segs, const int32_t* chunk_prefix, int n_segs, int total_chunks,
+                             int passes, hipStream_t s);
+// Large-n index build (before k_reorder) and rank, over every large job of a call.
+hipError_t launch_large_index(const DevJob* table, const LargeIndex* li, int n_large, const int32_t* chunk_prefix,
+                              int total_chunks, const SortSeg* segs, hipStream_t s);
+hipError_t launch_large_rank(const DevJob* table, const LargeRank* lr, int n_large, const int32_t* chunk_prefix,
+                             int total_chunks, const SortSeg* segs, const int32_t* seg_chunk_prefix,
+                             int total_seg_chunks, hipStream_t s);
 // Join kernel for dimensionality D, top-k capacity class kc and filter
 // flavour xf; grid == 0 asks for a persistent grid filling the device.
 hipError_t launch_join(int D, int kc, int xf, const JoinArgs& a, int grid, hipStream_t s);

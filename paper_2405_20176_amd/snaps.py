@@ -22,7 +22,8 @@ SNAPS_ENOMEM = -2
 SNAPS_EDEVICE = -3
 SNAPS_EUNSUPPORTED = -4
 OP_KNN, OP_EPS, OP_SCORES, OP_RANK = 0, 1, 2, 3
-MAX_N = 32768
+MAX_N = 1 << 30
+LDS_N = 32768          # jobs up to this size are indexed and ranked inside LDS
 MAX_K = 32
 
 
@@ -227,11 +228,14 @@ def snaps_outlier_scores(jobs: Sequence[Job], tune: Optional[c_tuning] = None, w
 
 
 def snaps_rank(eps_count: torch.Tensor, eps_mean: torch.Tensor, indeg: torch.Tensor, knn_mean: torch.Tensor,
-               rank: torch.Tensor, stream=None):
+               rank: torch.Tensor, ws: Optional[torch.Tensor] = None, stream=None):
     lib = load_library()
     n = eps_count.numel()
-    _check(lib.snaps_rank(_ptr(eps_count), _ptr(eps_mean), _ptr(indeg), _ptr(knn_mean), n, _ptr(rank), None, 0,
-                          _stream(stream)))
+    need = lib.snaps_workspace_bytes(OP_RANK, n, 0, 0)
+    if ws is None and need > 0:
+        ws = _workspace(need, eps_count.device)
+    _check(lib.snaps_rank(_ptr(eps_count), _ptr(eps_mean), _ptr(indeg), _ptr(knn_mean), n, _ptr(rank), _ptr(ws),
+                          0 if ws is None else ws.numel(), _stream(stream)))
 
 
 def score_space(pop: Population, mask: int, k: int, eps: float, tune: Optional[c_tuning] = None,

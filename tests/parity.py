@@ -129,8 +129,9 @@ def check_scores(gpu: dict, ora: dict, k: int, eps: float, check_ranks: bool = T
     return rep
 
 
-def check_knn(ids_g, dist_g, ora: dict, k: int, label: str = "") -> int:
-    """Neighbour lists of snaps_knn_selfjoin against the oracle."""
+def check_knn(ids_g, dist_g, ora: dict, k: int, label: str = "", row_ids=None) -> int:
+    """Neighbour lists of snaps_knn_selfjoin against the oracle; ``row_ids``
+    are the object ids of the rows (default: row i is object i)."""
     ids_g = np.asarray(ids_g).astype(np.int64)
     dist_g = np.asarray(dist_g, dtype=np.float64)
     dk = ora["knn_dist"][:, k - 1]
@@ -138,6 +139,8 @@ def check_knn(ids_g, dist_g, ora: dict, k: int, label: str = "") -> int:
     gap = np.where(np.isinf(dn), np.inf, (dn - dk) / np.where(dn > 0, dn, 1.0))
     strict = (gap > TAU) | ((dk == 0) & (dn == 0))
     n = ids_g.shape[0]
+    if row_ids is None:
+        row_ids = np.arange(n)
     assert (np.diff(dist_g, axis=1) >= 0).all(), f"{label} GPU distances not ascending"
     for i in range(n):
         if strict[i]:
@@ -146,7 +149,7 @@ def check_knn(ids_g, dist_g, ora: dict, k: int, label: str = "") -> int:
             inner = ora["knn_ids"][i][ora["knn_dist"][i] < dk[i] * (1 - TAU)]
             assert set(inner.tolist()) <= set(ids_g[i].tolist()), f"{label} exempt {i} misses a strict neighbour"
             assert (dist_g[i] <= dk[i] * (1 + TAU) + 1e-30).all()
-        assert i not in set(ids_g[i].tolist())
+        assert int(row_ids[i]) not in set(ids_g[i].tolist()), f"{label} object {row_ids[i]} is its own neighbour"
     od = ora["knn_dist"]
     rel = np.abs(np.sort(dist_g, axis=1) - od) / np.maximum(od, 1e-30)
     assert ((rel <= TAU) | ((od == 0) & (dist_g == 0))).all(), f"{label} kNN distances off"

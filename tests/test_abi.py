@@ -49,8 +49,11 @@ def test_workspace_sizes(lib):
     assert lib.snaps_workspace_bytes(OP_KNN, 100, 3, 100) == 0         # k > n-1
     assert lib.snaps_workspace_bytes(OP_KNN, 100, 17, 5) == 0          # d > 16
     assert lib.snaps_workspace_bytes(OP_EPS, 100, 3, 0) > 0
-    assert lib.snaps_workspace_bytes(OP_RANK, 100, 0, 0) == 0
-    assert lib.snaps_workspace_bytes(OP_SCORES, 40000, 3, 5) == 0      # beyond this version's n limit
+    assert lib.snaps_workspace_bytes(OP_RANK, 100, 0, 0) == 0          # LDS-resident rank needs none
+    assert lib.snaps_workspace_bytes(OP_RANK, 40000, 0, 0) > 8 * 40000 * 4
+    big = lib.snaps_workspace_bytes(OP_SCORES, 40000, 3, 5)            # device-wide sort path
+    assert big > lib.snaps_workspace_bytes(OP_KNN, 40000, 3, 5) > 0
+    assert lib.snaps_workspace_bytes(OP_SCORES, (1 << 30) + 1, 3, 5) == 0   # beyond the n limit
 
 
 def _pop(n=100, f=15):
@@ -89,7 +92,7 @@ def test_population_validation(lib):
            c_population(0x1000, 128, 100, 1), c_population(0x1000, 128, 100, 33)]
     for p in bad:
         assert lib.snaps_knn_selfjoin(ctypes.byref(p), 0b11, 1, c, None, None, 0, None) == -1
-    big = c_population(0x1000, 1 << 20, 1 << 20, 15)
+    big = c_population(0x1000, 1 << 31, 1 << 31, 15)
     assert lib.snaps_knn_selfjoin(ctypes.byref(big), 0b11, 1, c, None, None, 0, None) == -4
 
 
@@ -119,4 +122,6 @@ def test_rank_validation(lib):
     c = ctypes.c_void_p(0x2000)
     assert lib.snaps_rank(None, c, c, c, 10, c, None, 0, None) == -1
     assert lib.snaps_rank(c, c, c, c, 0, c, None, 0, None) == -1
-    assert lib.snaps_rank(c, c, c, c, 1 << 20, c, None, 0, None) == -4
+    assert lib.snaps_rank(c, c, c, c, 1 << 20, c, None, 0, None) == -1      # needs a workspace
+    assert lib.snaps_rank(c, c, c, c, 1 << 20, c, c, 10, None) == -2        # too small
+    assert lib.snaps_rank(c, c, c, c, 1 << 31, c, None, 0, None) == -4

@@ -78,9 +78,10 @@ def c0():
 
 @pytest.mark.parametrize("split", [1, 2, 4, 8])
 @pytest.mark.parametrize("mode", [1, 2])
-def test_c0_parity(S, c0, split, mode):
+@pytest.mark.parametrize("filt", [1, 2])
+def test_c0_parity(S, c0, split, mode, filt):
     x, k, eps = c0
-    g = run_gpu(S, x, 0b111, k, float(eps), S.tuning(mode=mode, split=split))
+    g = run_gpu(S, x, 0b111, k, float(eps), S.tuning(mode=mode, split=split, filter=filt))
     ora = run_oracle(x, 0b111, k, eps)
     rep = check_scores(g, ora, k, float(eps), label=f"C0 split={split} mode={mode}")
     # eps is the midpoint of two pair distances closer than tau: those two
@@ -101,6 +102,36 @@ def test_pruning_and_split_invariance_bitwise(S, c0):
     b = run_gpu(S, x, 0b111, k, float(eps), S.tuning(split=8))
     for key in ("eps_count", "indeg", "knn_mean"):
         np.testing.assert_array_equal(a[key], b[key])
+
+
+def _prefilter_cases():
+    rng = np.random.default_rng(77)
+    cases = [(G.gen_c0()[0], 0b111, 5, None)]
+    for d in (2, 3, 5, 8, 12, 15, 16):
+        x = rng.random((900, 16)).astype(np.float32)
+        mask = int(sum(1 << f for f in rng.choice(16, size=d, replace=False)))
+        cases.append((x, mask, 10, 0.1 * math.sqrt(d)))
+    dup = (rng.integers(0, 3, size=(300, 6)) / 3.0).astype(np.float32)
+    cases.append((dup, 0b111111, 20, 0.34))
+    off = (rng.random((500, 4)) * 0.001 + 0.9).astype(np.float32)   # large norms, tiny distances
+    cases.append((off, 0b1111, 7, 2e-4))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_prefilter_is_bitwise_identical_to_direct_form(S, case):
+    """The expanded-form prefilter only skips candidates that provably cannot
+    matter; every surviving candidate is re-evaluated in the direct form, so
+    all outputs equal those of the direct-form scan bit for bit."""
+    x, mask, k, eps = _prefilter_cases()[case]
+    if eps is None:
+        eps = float(O.eps_exact_mean_count(x, 10))
+    for split in (1, 4):
+        a = run_gpu(S, x, mask, k, eps, S.tuning(split=split, filter=1))
+        b = run_gpu(S, x, mask, k, eps, S.tuning(split=split, filter=2))
+        for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+            np.testing.assert_array_equal(a[key], b[key], err_msg=f"{key} case={case} split={split}")
+    check_scores(b, run_oracle(x, mask, k, eps), k, eps, label=f"prefilter case {case}")
 
 
 def test_determinism(S, c0):
@@ -250,3 +281,126 @@ def test_c1_full_size_spaces(S, c1, which):
     g = run_gpu(S, x, mask, k, eps)
     rep = check_scores(g, run_oracle(x, mask, k, eps), k, eps, label=f"C1 space {which}")
     assert rep["knn_exempt"] < 0.01 * x.shape[0]
+
+
+# ------------------------------------------------------------------ large n ---
+
+def sampled_check(S, x, mask, k, eps, jobs_out, n_samples=384, seed=0, label=""):
+    """Parity at sizes the full oracle cannot finish: exact float64 answers
+    for seeded sample objects (C twin, subset mode), GPU kNN lists for the
+    same objects, and properties that hold at any size (sum of in-degrees,
+    in-degree recomputed from the GPU's own kNN lists, rank self-consistency)."""
+    n = x.shape[0]
+    rng = np.random.default_rng(seed)
+    q = np.sort(rng.choice(n, size=min(n_samples, n), replace=False))
+    xs = O.project(x, mask).astype(np.float32)
+    ora = C.join(xs, k, float(eps), band=(float(eps) * (1 - TAU), float(eps) * (1 + TAU)), qids=q)
+    cnt = jobs_out["eps_count"]
+    mean = jobs_out["eps_mean"].astype(np.float64)
+    km = jobs_out["knn_mean"].astype(np.float64)
+    dk = ora["knn_dist"][:, k - 1]
+    o_km = ora["knn_dist"].sum(axis=1) / k
+    np.testing.assert_allclose(km[q], o_km, rtol=TAU, err_msg=f"{label} knn_mean")
+    exempt = ora["band"] > 0
+    assert ((cnt[q] == ora["eps_count"]) | exempt).all(), f"{label} eps_count"
+    o_mean = np.where(ora["eps_count"] > 0, ora["eps_sum"] / np.maximum(ora["eps_count"], 1), 0.0)
+    rel = np.abs(mean[q] - o_mean) / np.maximum(o_mean, 1e-30)
+    assert ((rel <= TAU) | exempt | ((o_mean == 0) & (mean[q] == 0))).all(), f"{label} eps_mean"
+    deg = jobs_out["indeg"].astype(np.int64)
+    assert deg.sum() == n * k
+    rg = jobs_out["rank"]
+    sr = self_ranks(cnt, jobs_out["eps_mean"], jobs_out["indeg"], jobs_out["knn_mean"])
+    for t in range(4):
+        assert (rg[t] == sr[t]).all(), f"{label} rank row {t}"
+    # kNN lists of the sample and in-degree recomputed from the GPU's own lists
+    pop = S.Population.from_rows(x)
+    ids = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    dist = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    S.snaps_knn_selfjoin(pop, mask, k, ids, dist)
+    torch.cuda.synchronize()
+    ids_h = ids.cpu().numpy()
+    sub = {"knn_ids": ora["knn_ids"], "knn_dist": ora["knn_dist"], "knn_next": ora["knn_next"]}
+    check_knn(ids_h[q], dist.cpu().numpy()[q], sub, k, label=label, row_ids=q)
+    np.testing.assert_array_equal(np.bincount(ids_h.ravel(), minlength=n), deg, err_msg=f"{label} indeg vs lists")
+    return int(exempt.sum())
+
+
+def _out(job):
+    return {key: getattr(job, key).cpu().numpy() for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank")}
+
+
+@pytest.mark.parametrize("n,d", [(32769, 3), (100_000, 2), (100_000, 6), (150_000, 12)])
+def test_large_n_device_wide_sort_path(S, n, d):
+    """n above one workgroup's LDS: index and ranks go through the device-wide
+    radix sort."""
+    rng = np.random.default_rng(n + d)
+    job = G.gen_c3_jobs(8)[0]
+    x = G.gen_c3_population(job, n=n)
+    mask = int(sum(1 << f for f in rng.choice(15, size=d, replace=False)))
+    eps = float(O.eps_sampled_mean_count(O.project(x, mask), 10, 64, seed=d))
+    pop = S.Population.from_rows(x)
+    j = S.Job.alloc(pop, mask, 10, eps)
+    S.snaps_outlier_scores([j])
+    torch.cuda.synchronize()
+    sampled_check(S, x, mask, 10, eps, _out(j), label=f"n={n} d={d}")
+
+
+def test_large_rank_entry_point(S):
+    rng = np.random.default_rng(19)
+    for n in (32769, 250_000):
+        cnt = rng.integers(0, 40, size=n).astype(np.int32)
+        mean = np.where(cnt > 0, rng.integers(0, 5000, size=n) / 77.0, 0.0).astype(np.float32)
+        deg = rng.integers(0, 30, size=n).astype(np.int32)
+        km = (rng.integers(0, 100000, size=n) / 13.0).astype(np.float32)
+        rank = torch.empty((4, n), dtype=torch.int32, device="cuda")
+        t = [torch.from_numpy(a).cuda() for a in (cnt, mean, deg, km)]
+        S.snaps_rank(*t, rank)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(rank.cpu().numpy(), self_ranks(cnt, mean, deg, km))
+
+
+def test_mixed_small_and_large_batch(S):
+    """One call mixing LDS-path and device-wide-path jobs gives the same
+    results as separate calls."""
+    rng = np.random.default_rng(4)
+    x = G.gen_c3_population(G.gen_c3_jobs(8)[1], n=60_000)
+    small = x[:20_000]
+    pl, ps = S.Population.from_rows(x), S.Population.from_rows(small)
+    specs = [(pl, 0b111, 5, 0.02), (ps, 0b1100000011, 10, 0.05), (pl, 0b11110000, 20, 0.08),
+             (ps, 0b11, 10, 0.004)]
+    tune = S.tuning(split=1)
+    jobs = [S.Job.alloc(p, m, k, e) for p, m, k, e in specs]
+    S.snaps_outlier_scores(jobs, tune)
+    torch.cuda.synchronize()
+    for (p, m, k, e), job in zip(specs, jobs):
+        one = S.Job.alloc(p, m, k, e)
+        S.snaps_outlier_scores([one], tune)
+        torch.cuda.synchronize()
+        for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+            assert torch.equal(getattr(job, key), getattr(one, key)), f"{key} mask={m:x}"
+
+
+@pytest.fixture(scope="module")
+def c2():
+    x, masks, k, target = G.gen_c2()
+    return x, masks, k, target
+
+
+@pytest.mark.parametrize("which", [0, 1, 57])
+def test_c2_lsst_scale_spaces(S, c2, which):
+    """LSST-scale population (5,000,000 objects): the full 15-feature space and
+    two of the 105 two-feature spaces, eps for a mean of 20 neighbours;
+    sampled exact checks plus whole-array properties."""
+    x, masks, k, target = c2
+    mask = int(masks[which])
+    xs = O.project(x, mask)
+    eps = float(O.eps_sampled_mean_count(xs, target, 24, seed=mask))
+    del xs
+    pop = S.Population.from_rows(x)
+    j = S.Job.alloc(pop, mask, k, eps)
+    S.snaps_outlier_scores([j])
+    torch.cuda.synchronize()
+    out = _out(j)
+    del j
+    ex = sampled_check(S, x, mask, k, eps, out, n_samples=128, seed=which, label=f"C2 space {which}")
+    assert ex <= 5

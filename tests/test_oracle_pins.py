@@ -367,3 +367,15 @@ def test_c_twin_matches_numpy_oracle():
         np.testing.assert_array_equal(a["eps_count"], b["eps_count"])
         np.testing.assert_allclose(a["eps_mean"], b["eps_mean"], rtol=1e-13)
         np.testing.assert_array_equal(a["rank"][[0, 2, 3]], b["rank"][[0, 2, 3]])
+
+
+def test_c_twin_query_subset_mode():
+    """The subset mode (used for sampled parity at large n) returns exactly
+    the rows of the full self-join."""
+    rng = np.random.default_rng(31)
+    x = (rng.integers(0, 40, size=(700, 4)) / 40.0).astype(np.float32)
+    full = C.join(x, 7, 0.2, band=(0.19, 0.21))
+    q = np.array([0, 5, 123, 699, 350])
+    sub = C.join(x, 7, 0.2, band=(0.19, 0.21), qids=q)
+    for key in ("knn_ids", "knn_dist", "knn_next", "eps_count", "eps_sum", "band"):
+        np.testing.assert_array_equal(sub[key], full[key][q])
