@@ -6,9 +6,11 @@ synthetic stand-in for the SNAPShot1 catalogue), all 32,752 subspaces of 2..15
 features, k = 10, eps per subspace from the stored table (mean neighbour count
 10).  A step runs the whole hot path for every subspace: index build, fused
 kNN + eps join with the four metrics, dense ranks.  Outputs of all subspaces
-stay resident in HBM (33 GB).  The timed steps use the batched form (thousands
-of subspaces per library call); a plain pass (one library call per subspace)
-is timed once afterwards for comparison.
+stay resident in HBM (31 GiB).  The timed steps use the batched form: every
+subspace in one job table, its three passes captured as HIP graphs and
+replayed.  A plain pass (one library call per subspace) is timed once
+afterwards for comparison, and the served form (alerts scored against
+resident populations under continuous batching) reports p50/p99 latency.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
@@ -68,6 +70,69 @@ def cpu_baseline(x, masks, eps_tab, k):
             "extrapolated_s": total, "cpu_model": _cpu_model()}
 
 
+def serve_bench(S, G, dev, seconds: float, spaces_per_pop: int = 4, n_streams: int = 4):
+    """Served form: 4 resident populations of 1,000,000 objects (the serving
+    generator), the first `spaces_per_pop` subspaces of each population's
+    seeded catalogue resident as scoring states, and an open-loop Poisson
+    stream (200 requests/s, 1..10,000 alerts per request, log-uniform) replayed
+    in real time through the continuous-batching server.  Requests naming a
+    non-resident catalogue entry are mapped onto the resident ones."""
+    import torch
+    from paper_2405_20176_amd.serve import Admission, Batcher, GpuExecutor, Request
+    w = G.gen_c4()
+    masks_tab, eps_tab = G.load_c4_eps()
+    t0 = time.perf_counter()
+    pops, bounds, states = [], [], {}
+    build_s = []
+    for p in range(w.n_pop):
+        x, lo, hi = w.population(p)
+        pop = S.Population.from_rows(x, device=dev)
+        del x
+        pops.append(pop)
+        bounds.append((lo, hi))
+        for si in range(spaces_per_pop):
+            m = int(masks_tab[p, si])
+            assert m == int(w.spaces[p][si])
+            tb = time.perf_counter()
+            states[(p, m)] = S.ServeState(pop, m, w.k, float(eps_tab[p, si]))
+            torch.cuda.synchronize()
+            build_s.append(time.perf_counter() - tb)
+    log(f"serving: {len(states)} states built in {time.perf_counter() - t0:.1f} s "
+        f"(cold build per state {np.median(build_s):.2f} s median)")
+    reqs = []
+    for r in w.requests(seconds):
+        p = r.pop
+        m = int(masks_tab[p, r.space % spaces_per_pop])
+        cols = G.mask_features(m)
+        lo, hi = bounds[p]
+        al = np.ascontiguousarray(w.alerts(r, lo, hi)[:, cols], dtype=np.float32)
+        reqs.append(Request(r.rid, r.arrival_s, (p, m), al))
+    n_alerts = sum(q.m for q in reqs)
+    log(f"serving: {len(reqs)} requests, {n_alerts} alerts over {seconds:.0f} s of arrivals")
+    ex = GpuExecutor(states, n_streams=n_streams, device=dev)
+    # warm-up: one request per state, not timed
+    warm = Batcher(ex, Admission(8 << 30, n_streams))
+    for i, key in enumerate(states):
+        warm.submit(Request(-1 - i, 0.0, key, np.zeros((64, bin(key[1]).count("1")), np.float32)))
+    warm.drain()
+    b = Batcher(ex, Admission(8 << 30, n_streams), max_batch_alerts=1 << 16)
+    t_start = time.perf_counter()
+    b.run_open_loop(reqs)
+    t_end = time.perf_counter()
+    lat = b.latencies()
+    done = [r for r in b.finished if r.status == "done"]
+    span = max(r.done for r in done) - min(r.arrival for r in done)
+    res = {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "mean_ms": float(lat.mean() * 1e3), "requests": len(done), "rejected": len(b.finished) - len(done),
+           "alerts": int(sum(r.m for r in done)), "alert_scores_per_s": float(sum(r.m for r in done) / span),
+           "wall_s": t_end - t_start, "arrival_rate_hz": w.rate_hz, "populations": w.n_pop, "population_n": w.pop_n,
+           "resident_states": len(states), "state_build_s_median": float(np.median(build_s)), "k": w.k,
+           "form": "continuous batching over 4 streams, admission by an 8 GiB in-flight budget"}
+    log(f"serving: p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms, "
+        f"{res['alert_scores_per_s']:.3e} alert scores/s")
+    return res
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -84,7 +149,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--chunk", type=int, default=4096, help="subspaces per library call in the batched form")
+    ap.add_argument("--chunk", type=int, default=0, help="subspaces per batched plan (0: all in one)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving run length (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-subspace pass")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--spaces", type=int, default=0, help="debug: use only the first N subspaces")
@@ -133,34 +199,36 @@ def main():
         j.out = S.c_scores(out_cnt[i].data_ptr(), out_mean[i].data_ptr(), out_deg[i].data_ptr(),
                            out_kmean[i].data_ptr())
         j.rank = out_rank[i].data_ptr()
-    chunks = [(s, min(n_sp, s + a.chunk)) for s in range(0, n_sp, a.chunk)]
+    chunk = a.chunk if a.chunk > 0 else n_sp
+    chunks = [(s, min(n_sp, s + chunk)) for s in range(0, n_sp, chunk)]
     job_ptr = lambda s: ctypes.cast(ctypes.byref(jobs, s * ctypes.sizeof(S.c_job)), ctypes.POINTER(S.c_job))
     stats = torch.zeros(4, dtype=torch.int64, device=dev)
     tunes = {p: S.tuning(passes=p, stats=stats if p == S.PASS_JOIN else None)
              for p in (S.PASS_INDEX, S.PASS_JOIN, S.PASS_RANK)}
-    ws_bytes = max(lib.snaps_outlier_scores_workspace(job_ptr(s), e - s, ctypes.byref(tunes[S.PASS_JOIN]))
-                   for s, e in chunks)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    log(f"{len(chunks)} chunks, workspace {ws_bytes / 2**30:.2f} GiB, outputs {n_sp * n * 32 / 2**30:.1f} GiB")
-
-    def call(s, e, tune):
-        rc = lib.snaps_outlier_scores(job_ptr(s), e - s, ctypes.byref(tune), ctypes.c_void_p(ws.data_ptr()),
-                                      ws_bytes, sptr)
-        if rc != 0:
-            raise RuntimeError(f"snaps_outlier_scores failed ({rc}): {S.last_error()}")
+    t_plan = time.perf_counter()
+    plans = []
+    for s0, e0 in chunks:
+        need = lib.snaps_outlier_scores_workspace(job_ptr(s0), e0 - s0, ctypes.byref(tunes[S.PASS_JOIN]))
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        trio = [S.Plan(None, tunes[p], ws=ws, c_jobs=job_ptr(s0), n_jobs=e0 - s0)
+                for p in (S.PASS_INDEX, S.PASS_JOIN, S.PASS_RANK)]
+        plans.append((ws, trio))
+    ws_total = sum(w.numel() for w, _ in plans)
+    log(f"{len(chunks)} plan(s) of 3 graphs built in {time.perf_counter() - t_plan:.1f} s, workspace "
+        f"{ws_total / 2**30:.2f} GiB, outputs {n_sp * n * 32 / 2**30:.1f} GiB")
 
     def step(events=None):
-        for s, e in chunks:
-            call(s, e, tunes[S.PASS_INDEX])
+        for _, (p_index, p_join, p_rank) in plans:
+            p_index.launch(stream)
             if events is not None:
                 ev0 = torch.cuda.Event(enable_timing=True)
                 ev1 = torch.cuda.Event(enable_timing=True)
                 ev0.record(stream)
-            call(s, e, tunes[S.PASS_JOIN])
+            p_join.launch(stream)
             if events is not None:
                 ev1.record(stream)
                 events.append((ev0, ev1))
-            call(s, e, tunes[S.PASS_RANK])
+            p_rank.launch(stream)
 
     for w in range(a.warmup):
         t = time.perf_counter()
@@ -195,8 +263,9 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded SNAPShot1-shaped generator; the catalogue itself is not available)",
         "config": {"workload": "SNAPShot1-shaped full run: N=31,693 objects x 15 features, all 32,752 subspaces "
-                               "(d=2..15), k=10, per-subspace eps for mean neighbour count 10, batched form",
-                   "n_objects": n, "n_subspaces": n_sp, "k": k, "subspaces_per_call": a.chunk},
+                               "(d=2..15), k=10, per-subspace eps for mean neighbour count 10, batched form "
+                               "(one job table, passes replayed as HIP graphs)",
+                   "n_objects": n, "n_subspaces": n_sp, "k": k, "subspaces_per_plan": chunk},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
                      "kernel": "k_join (fused kNN + eps join), all instantiations",
@@ -225,6 +294,11 @@ def main():
                            "form": "one library call per subspace, one stream", "passes": 1}
         result["batched_over_plain"] = value / result["plain"]["value"]
         log(f"plain: {plain_s:.2f} s per pass")
+
+    if a.serve_seconds > 0:
+        del plans
+        torch.cuda.empty_cache()
+        result["serving"] = serve_bench(S, G, dev, a.serve_seconds)
 
     if not a.no_cpu:
         cb = cpu_baseline(x, masks if not a.spaces else G.all_masks(), G.load_c1_eps(), k)

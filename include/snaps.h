@@ -112,7 +112,10 @@ typedef struct {
     int32_t passes;         /* 0 = all; else a mask of SNAPS_PASS_*.  A call that runs the join
                                or rank pass without the index pass must follow a call with the
                                same jobs and workspace that ran the earlier passes. */
-    int32_t reserved[3];    /* must be 0 */
+    int32_t mq;             /* 0 auto, else waves per workgroup that take consecutive query tiles
+                               of one job and walk the same candidate tiles in lockstep: 1, 2,
+                               4 or 8 (1 = off).  Used only when split is 1. */
+    int32_t reserved[2];    /* must be 0 */
     uint64_t* stats;        /* optional device uint64[4], accumulated (never cleared) by the
                                join pass: [0] query-candidate pairs evaluated, [1] candidate
                                tiles scanned, [2] candidate tiles skipped, [3] pairs evaluated
@@ -178,6 +181,20 @@ int snaps_eps_selfjoin(const snaps_population* P, uint32_t mask, float eps,
 int snaps_outlier_scores(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune,
                          void* ws, size_t ws_bytes, void* stream);
 
+/* Batched form as a replayable HIP graph.  snaps_plan_create validates the
+ * jobs, uploads their table into `ws` once (waiting for `stream`), and
+ * captures the launches of the selected passes (tune->passes, all by
+ * default) into a graph; snaps_plan_launch replays it on a stream.  Every
+ * replay recomputes the same jobs into the same outputs; the jobs' inputs,
+ * outputs and `ws` must stay allocated while the plan exists, and replays
+ * that overlap on different streams race.  Several plans of different
+ * passes may share jobs and workspace (run them in pass order). */
+typedef struct snaps_plan snaps_plan;
+int snaps_plan_create(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune,
+                      void* ws, size_t ws_bytes, void* stream, snaps_plan** plan);
+int snaps_plan_launch(const snaps_plan* plan, void* stream);
+void snaps_plan_destroy(snaps_plan* plan);
+
 /* Dense rankings of the four metrics of one job (Sec. 3.4, Tab. 2): rank 0
  * is the most outlying; eps_count and indeg rank ascending, eps_mean and
  * knn_mean descending, and objects with eps_count == 0 rank first on
@@ -190,6 +207,55 @@ int snaps_outlier_scores(const snaps_job* jobs, int32_t n_jobs, const snaps_tuni
 int snaps_rank(const int32_t* eps_count, const float* eps_mean, const int32_t* indeg,
                const float* knn_mean, int64_t n, int32_t* rank,
                void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- serving
+ *
+ * Scoring new objects ("alerts") against a resident population in one
+ * subspace.  The paper has no serving path; an alert is scored as one extra
+ * object that changes nothing in the population and sees no other alert:
+ * its k nearest population objects and their mean distance, its population
+ * neighbours within eps (count and mean distance), its in-degree (the number
+ * of population objects whose own k-th neighbour distance is strictly larger
+ * than their distance to the alert), and on each metric the number of
+ * distinct population values strictly more outlying than its own (its dense
+ * rank position).  Results therefore do not depend on which other alerts
+ * share a call. */
+
+/* Device bytes of the resident state of (P, mask, k); 0 for invalid input. */
+size_t snaps_serve_state_bytes(const snaps_population* P, uint32_t mask, int32_t k);
+
+/* Build the resident state into caller-owned device memory `state`: runs the
+ * full self-join of P in `mask` (index, both joins, metrics, ranks) and keeps
+ * what alert scoring needs.  The state refers to P->cols, which must stay
+ * allocated and unchanged while the state is used.  Asynchronous on stream. */
+int snaps_serve_state_build(const snaps_population* P, uint32_t mask, int32_t k, float eps,
+                            void* state, size_t state_bytes, void* stream);
+
+/* Device pointers, inside a built state, of the population's own four
+ * metrics ([n] each) and ranks ([4][n]).  Pure host function. */
+int snaps_serve_state_outputs(const void* state, int64_t n, int32_t d, int32_t k,
+                              const int32_t** eps_count, const float** eps_mean,
+                              const int32_t** indeg, const float** knn_mean,
+                              const int32_t** rank);
+
+/* One batch of alerts for one built state (all device pointers). */
+typedef struct {
+    const void* state;      /* built by snaps_serve_state_build */
+    const float* alerts;    /* [m][d] row-major, the subspace's columns in ascending
+                               feature order, normalised with the population's bounds */
+    int32_t m;              /* number of alerts (0 allowed) */
+    int32_t pad0;
+    int32_t* eps_count;     /* [m] outputs */
+    float* eps_mean;
+    int32_t* indeg;
+    float* knn_mean;
+    int32_t* rank;          /* [4][m] or NULL */
+} snaps_alert_job;
+
+/* Score n_jobs alert batches whose states all have dimensionality d and the
+ * same k (the job list is host memory, read during the call).  Jobs may use
+ * different states and populations.  Asynchronous on stream. */
+int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k, void* stream);
 
 #ifdef __cplusplus
 }

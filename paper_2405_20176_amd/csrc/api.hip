@@ -86,7 +86,10 @@ int check_tuning(const snaps_tuning* t) {
     if (t->index_dims < 0 || t->index_dims > kMaxIndexDims) return fail(SNAPS_EINVAL, "tuning.index_dims must be in [0, 6]");
     if (t->filter < 0 || t->filter > 2) return fail(SNAPS_EINVAL, "tuning.filter must be 0, 1 or 2");
     if (t->passes < 0 || t->passes > 7) return fail(SNAPS_EINVAL, "tuning.passes must be a mask of SNAPS_PASS_*");
-    for (int i = 0; i < 3; ++i)
+    if (!(t->mq == 0 || t->mq == 1 || t->mq == 2 || t->mq == 4 || t->mq == 8))
+        return fail(SNAPS_EINVAL, "tuning.mq must be 0, 1, 2, 4 or 8");
+    if (t->mq > 1 && t->split > 1) return fail(SNAPS_EINVAL, "tuning.mq and tuning.split cannot both exceed 1");
+    for (int i = 0; i < 2; ++i)
         if (t->reserved[i] != 0) return fail(SNAPS_EINVAL, "tuning.reserved must be zero");
     return SNAPS_OK;
 }
@@ -126,7 +129,7 @@ struct JobPlan {
     size_t bytes;
 };
 
-JobPlan plan_job(int64_t n, int d, int k, bool with_rank) {
+JobPlan plan_job(int64_t n, int d, int k, bool with_rank, bool force_large = false) {
     JobPlan p{};
     p.n = (int32_t)n;
     p.d = d;
@@ -134,7 +137,7 @@ JobPlan plan_job(int64_t n, int d, int k, bool with_rank) {
     p.kc = kc_class(k);
     p.ntiles = (int32_t)((n + kTile - 1) / kTile);
     p.nchunks = (int32_t)((n + kRadixChunk - 1) / kRadixChunk);
-    p.large = n > kLdsSortMax;
+    p.large = force_large || n > kLdsSortMax;
     p.rank = with_rank;
     const size_t rows = (size_t)p.ntiles * kTile;
     const int dp = row_stride(d);
@@ -191,9 +194,9 @@ MetaLayout meta_layout(int n_jobs, int n_large, int n_lrank) {
     };
     m.table = take((size_t)n_jobs * sizeof(DevJob));
     m.order = take((size_t)n_jobs * sizeof(int32_t));
-    m.unit_prefix = take((size_t)(n_jobs + kNumClasses) * sizeof(int32_t));
+    m.unit_prefix = take((size_t)(n_jobs + kNumClasses * kQueues) * sizeof(int32_t));
     m.tile_prefix = take((size_t)(n_jobs + 1) * sizeof(int32_t));
-    m.counters = take((size_t)kNumClasses * sizeof(int32_t));
+    m.counters = take((size_t)kNumClasses * kQueues * sizeof(int32_t));
     m.li = take((size_t)n_large * sizeof(LargeIndex));
     m.iseg = take((size_t)n_large * sizeof(SortSeg));
     m.ichunk = take((size_t)(n_large + 1) * sizeof(int32_t));
@@ -206,7 +209,7 @@ MetaLayout meta_layout(int n_jobs, int n_large, int n_lrank) {
 }
 
 struct Tune {
-    int mode = 0, split = 0, index_dims = 0, filter = 0, passes = 7;
+    int mode = 0, split = 0, index_dims = 0, filter = 0, passes = 7, mq = 0;
     unsigned long long* stats = nullptr;
 };
 
@@ -218,6 +221,7 @@ Tune resolve_tune(const snaps_tuning* t) {
         r.index_dims = t->index_dims;
         r.filter = t->filter;
         r.passes = t->passes ? t->passes : 7;
+        r.mq = t->mq;
         r.stats = reinterpret_cast<unsigned long long*>(t->stats);
     }
     return r;
@@ -272,34 +276,59 @@ int choose_split(const Tune& tn, int64_t total_units, int cus, int kc) {
     return s;
 }
 
-// Launch the join kernels of every class present; `units` is per class.
-int launch_joins(const Meta& meta, const std::vector<int>& class_of_slot, const std::vector<int>& cls_count,
-                 const std::vector<int>& cls_units, const std::vector<int>& cls_order_off,
-                 const std::vector<int>& cls_prefix_off, const Tune& tn, int cus, hipStream_t s) {
-    (void)class_of_slot;
+// Waves per lockstep workgroup: off unless asked for (measured on MI355X: the
+// per-tile barrier costs more than the shared scalar-cache lines save when
+// tiles are pruned).
+int choose_mq(const Tune& tn, int64_t units1, int cus) {
+    (void)units1;
+    (void)cus;
+    if (tn.split > 1) return 1;
+    return tn.mq > 0 ? tn.mq : 1;
+}
+
+// Per kernel class: its jobs dealt round-robin (most expensive first) over
+// the per-XCD work queues.
+struct ClassPlan {
+    int count = 0;
+    int units = 0;
+    int q_order_off[kQueues] = {};
+    int q_prefix_off[kQueues] = {};
+    int q_jobs[kQueues] = {};
+    int q_units[kQueues] = {};
+};
+
+// Launch the join kernels of every class present.
+int launch_joins(const Meta& meta, const std::vector<ClassPlan>& plans, const Tune& tn, int mq, int cus,
+                 hipStream_t s) {
     int64_t all_units = 0;
-    for (int c = 0; c < kNumClasses; ++c) all_units += cls_units[c];
+    for (const auto& p : plans) all_units += p.units;
     const int xf = tn.filter == 1 ? 0 : 1;
     hipError_t fe = launch_fill_i32(meta.counters, meta.n_counters, 0, s);
     if (fe != hipSuccess) return hip_fail(fe, "counter reset");
     for (int c = 0; c < kNumClasses; ++c) {
-        if (cls_count[c] == 0) continue;
+        const ClassPlan& p = plans[c];
+        if (p.count == 0) continue;
         const int d = c / 5;
         static const int kKc[5] = {0, 5, 10, 20, 32};
         const int kc = kKc[c % 5];
-        const int split = choose_split(tn, all_units, cus, kc);
+        const int split = mq > 1 ? 1 : choose_split(tn, all_units, cus, kc);
         JoinArgs a{};
         a.table = meta.table;
-        a.order = meta.order + cls_order_off[c];
-        a.unit_prefix = meta.unit_prefix + cls_prefix_off[c];
-        a.n_class_jobs = cls_count[c];
-        a.total_units = cls_units[c];
-        a.counter = meta.counters + c;
+        a.order = meta.order;
+        a.unit_prefix = meta.unit_prefix;
+        for (int q = 0; q < kQueues; ++q) {
+            a.q_order_off[q] = p.q_order_off[q];
+            a.q_prefix_off[q] = p.q_prefix_off[q];
+            a.q_jobs[q] = p.q_jobs[q];
+            a.q_units[q] = p.q_units[q];
+        }
+        a.counter = meta.counters + c * kQueues;
         a.split = split;
+        a.mq = mq;
         a.stats = tn.stats;
-        const int per_cu = join_blocks_per_cu(d, kc, xf, split);
+        const int per_cu = join_blocks_per_cu(d, kc, xf, split, mq);
         if (per_cu <= 0) return fail(SNAPS_EDEVICE, "no occupancy for join kernel d=%d kc=%d split=%d", d, kc, split);
-        int grid = std::min<int64_t>((int64_t)per_cu * cus, cls_units[c]);
+        int grid = std::min<int64_t>((int64_t)per_cu * cus, p.units);
         hipError_t e = launch_join(d, kc, xf, a, grid, s);
         if (e != hipSuccess) return hip_fail(e, "join kernel launch");
     }
@@ -319,6 +348,7 @@ struct RunJob {
     int32_t* rank;
     int32_t* knn_ids;
     float* knn_dist;
+    float* knn_kth;
 };
 
 void count_large(const std::vector<RunJob>& jobs, int* n_large, int* n_lrank) {
@@ -345,7 +375,13 @@ std::vector<uint8_t>& staging() {
     return buf;
 }
 
-int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_bytes, hipStream_t s) {
+// How run() treats the metadata block of a multi-job or large-job call:
+// upload it and launch (normal calls), upload only (before a graph capture),
+// or launch only (inside a capture, after an upload of the same jobs).
+enum class RunMode { Full, UploadOnly, LaunchOnly };
+
+int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_bytes, hipStream_t s,
+        RunMode mode = RunMode::Full) {
     const int n_jobs = (int)jobs.size();
     const size_t need = run_workspace(jobs);
     if (!ws && need > 0) return fail(SNAPS_EINVAL, "workspace is NULL (%zu bytes needed)", need);
@@ -364,7 +400,7 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
     meta.unit_prefix = reinterpret_cast<int32_t*>(base + ml.unit_prefix);
     meta.tile_prefix = reinterpret_cast<int32_t*>(base + ml.tile_prefix);
     meta.counters = reinterpret_cast<int32_t*>(base + ml.counters);
-    meta.n_counters = kNumClasses;
+    meta.n_counters = kNumClasses * kQueues;
 
     std::vector<DevJob> table(n_jobs);
     std::vector<char*> job_base(n_jobs);
@@ -382,6 +418,7 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         j.rank = r.rank;
         j.knn_ids = r.knn_ids;
         j.knn_dist = r.knn_dist;
+        j.knn_kth = r.knn_kth;
         table[i] = j;
         off += r.plan.bytes;
         total_tiles += r.plan.ntiles;
@@ -390,30 +427,44 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
     }
 
     // Group jobs into kernel classes (dimensionality, top-k capacity); within
-    // a class, the most expensive jobs (largest n) go first.
-    std::vector<int> cls_count(kNumClasses, 0), cls_units(kNumClasses, 0);
-    std::vector<int> cls_order_off(kNumClasses, 0), cls_prefix_off(kNumClasses, 0);
+    // a class, the most expensive jobs (largest n) first, dealt round-robin
+    // over the per-XCD queues.
     std::vector<std::vector<int>> members(kNumClasses);
     for (int i = 0; i < n_jobs; ++i) members[class_id(jobs[i].plan.d, jobs[i].plan.kc)].push_back(i);
+    int64_t units1 = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const int ql = join_ql(jobs[i].plan.kc);
+        units1 += (jobs[i].plan.ntiles + ql - 1) / ql;
+    }
+    const int mq = choose_mq(tn, units1, di.cus);
+    std::vector<ClassPlan> plans(kNumClasses);
     std::vector<int32_t> order;
     std::vector<int32_t> unit_prefix;
     order.reserve(n_jobs);
-    unit_prefix.reserve(n_jobs + kNumClasses);
+    unit_prefix.reserve(n_jobs + kNumClasses * kQueues);
     for (int c = 0; c < kNumClasses; ++c) {
         auto& m = members[c];
         std::stable_sort(m.begin(), m.end(), [&](int a, int b) { return jobs[a].plan.n > jobs[b].plan.n; });
-        cls_count[c] = (int)m.size();
-        cls_order_off[c] = (int)order.size();
-        cls_prefix_off[c] = (int)unit_prefix.size();
-        int64_t acc = 0;
-        unit_prefix.push_back(0);
-        const int ql = join_ql(c % 5 == 0 ? 0 : (c % 5 == 4 ? 32 : 5));
-        for (int i : m) {
-            order.push_back(i);
-            acc += (jobs[i].plan.ntiles + ql - 1) / ql;
-            unit_prefix.push_back((int32_t)acc);
+        ClassPlan& p = plans[c];
+        p.count = (int)m.size();
+        if (p.count == 0) continue;
+        static const int kKcOf[5] = {0, 5, 10, 20, 32};
+        const int per_unit = join_ql(kKcOf[c % 5]) * mq;      // query tiles per work unit
+        for (int q = 0; q < kQueues; ++q) {
+            p.q_order_off[q] = (int)order.size();
+            p.q_prefix_off[q] = (int)unit_prefix.size();
+            int64_t acc = 0;
+            unit_prefix.push_back(0);
+            for (size_t t = q; t < m.size(); t += kQueues) {
+                const int i = m[t];
+                order.push_back(i);
+                acc += (jobs[i].plan.ntiles + per_unit - 1) / per_unit;
+                unit_prefix.push_back((int32_t)acc);
+            }
+            p.q_jobs[q] = (int)((m.size() + kQueues - 1 - q) / kQueues);
+            p.q_units[q] = (int)acc;
+            p.units += (int)acc;
         }
-        cls_units[c] = (int)acc;
     }
 
     // Device-wide sort descriptors of the large jobs.
@@ -483,20 +534,20 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         // The metadata of a single small job is written by its index kernel
         // from kernel arguments (no host-to-device copy); later passes of the
         // same job reuse it.
-        cls_order_off.assign(kNumClasses, 0);
-        cls_prefix_off.assign(kNumClasses, 0);
-        if (do_index) {
+        // (the single job is the first entry of order and unit_prefix)
+        if (do_index && mode != RunMode::UploadOnly) {
             IndexArgs ia{};
             ia.meta = meta;
             ia.n_jobs = 1;
             ia.seed = 1;
-            ia.single_units = unit_prefix.back();
+            const ClassPlan& p = plans[class_id(jobs[0].plan.d, jobs[0].plan.kc)];
+            ia.single_units = p.q_units[0];
             ia.single_tiles = table[0].ntiles;
             ia.single = table[0];
             e = launch_index_sort(ia, 1, s);
             if (e != hipSuccess) return hip_fail(e, "index sort launch");
         }
-    } else {
+    } else if (mode != RunMode::LaunchOnly) {
         // One host-to-device copy of the metadata block (synchronous for
         // pageable host memory, so the staging buffer can be reused).
         auto& st = staging();
@@ -517,6 +568,9 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         put(ml.rsegchunk, rsegchunk.data(), rsegchunk.size() * sizeof(int32_t));
         e = hipMemcpyAsync(base, st.data(), ml.bytes, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "job table upload");
+    }
+    if (mode == RunMode::UploadOnly) return SNAPS_OK;
+    if (!seed_single) {
         if (do_index) {
             IndexArgs ia{};
             ia.meta = meta;
@@ -535,7 +589,7 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         if (e != hipSuccess) return hip_fail(e, "reorder launch");
     }
     if (do_join) {
-        rc = launch_joins(meta, {}, cls_count, cls_units, cls_order_off, cls_prefix_off, tn, di.cus, s);
+        rc = launch_joins(meta, plans, tn, mq, di.cus, s);
         if (rc != SNAPS_OK) return rc;
     }
     bool any_rank = false;
@@ -731,6 +785,238 @@ int snaps_rank(const int32_t* eps_count, const float* eps_mean, const int32_t* i
                           reinterpret_cast<const SortSeg*>(base + ml.rseg),
                           reinterpret_cast<const int32_t*>(base + ml.rsegchunk), 4 * nchunks, s);
     if (e != hipSuccess) return hip_fail(e, "large rank launch");
+    return SNAPS_OK;
+}
+
+// -------------------------------------------------------------- graph plans
+
+struct snaps_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int snaps_plan_create(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune, void* ws, size_t ws_bytes,
+                      void* stream, snaps_plan** out) {
+    if (!out) return fail(SNAPS_EINVAL, "plan output pointer is NULL");
+    *out = nullptr;
+    int rc = check_tuning(tune);
+    if (rc != SNAPS_OK) return rc;
+    std::vector<RunJob> rj;
+    rc = collect_jobs(jobs, n_jobs, &rj);
+    if (rc != SNAPS_OK) return rc;
+    const Tune tn = resolve_tune(tune);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // Upload the job table once, then capture the launches on a private
+    // stream (the upload is not part of the graph).
+    rc = run(rj, tn, ws, ws_bytes, s, RunMode::UploadOnly);
+    if (rc != SNAPS_OK) return rc;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "plan upload");
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        hipStreamDestroy(cs);
+        return hip_fail(e, "begin capture");
+    }
+    rc = run(rj, tn, ws, ws_bytes, cs, RunMode::LaunchOnly);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    hipStreamDestroy(cs);
+    if (rc != SNAPS_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return hip_fail(e, "graph instantiate");
+    }
+    snaps_plan* p = new snaps_plan;
+    p->graph = g;
+    p->exec = x;
+    *out = p;
+    return SNAPS_OK;
+}
+
+int snaps_plan_launch(const snaps_plan* plan, void* stream) {
+    if (!plan || !plan->exec) return fail(SNAPS_EINVAL, "plan is NULL");
+    hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return SNAPS_OK;
+}
+
+void snaps_plan_destroy(snaps_plan* plan) {
+    if (!plan) return;
+    if (plan->exec) hipGraphExecDestroy(plan->exec);
+    if (plan->graph) hipGraphDestroy(plan->graph);
+    delete plan;
+}
+
+// ------------------------------------------------------------------ serving
+
+namespace {
+
+struct ServeLayout {
+    JobPlan plan;
+    size_t hdr, ws, ws_bytes, rk2, tmax, tkey, cnt, mean, deg, kmean, kth, rank, bytes;
+};
+
+ServeLayout serve_layout(int64_t n, int d, int k) {
+    ServeLayout L{};
+    L.plan = plan_job(n, d, k, true, true);
+    const size_t rows = (size_t)L.plan.ntiles * kTile;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += align_up(b);
+        return o;
+    };
+    L.hdr = take(sizeof(ServeState));
+    L.ws_bytes = meta_layout(1, 1, 1).bytes + L.plan.bytes;
+    L.ws = take(L.ws_bytes);
+    L.rk2 = take(rows * sizeof(float));
+    L.tmax = take((size_t)L.plan.ntiles * sizeof(float));
+    L.tkey = take((size_t)L.plan.ntiles * sizeof(uint32_t));
+    L.cnt = take((size_t)n * 4);
+    L.mean = take((size_t)n * 4);
+    L.deg = take((size_t)n * 4);
+    L.kmean = take((size_t)n * 4);
+    L.kth = take((size_t)n * 4);
+    L.rank = take((size_t)4 * n * 4);
+    L.bytes = off;
+    return L;
+}
+
+}  // namespace
+
+size_t snaps_serve_state_bytes(const snaps_population* P, uint32_t mask, int32_t k) {
+    if (check_population(P, mask) != SNAPS_OK || check_k(P->n, k) != SNAPS_OK) return 0;
+    return serve_layout(P->n, popcount32(mask), k).bytes;
+}
+
+int snaps_serve_state_build(const snaps_population* P, uint32_t mask, int32_t k, float eps, void* state,
+                            size_t state_bytes, void* stream) {
+    int rc = check_population(P, mask);
+    if (rc != SNAPS_OK) return rc;
+    rc = check_k(P->n, k);
+    if (rc != SNAPS_OK) return rc;
+    rc = check_eps(eps);
+    if (rc != SNAPS_OK) return rc;
+    const int d = popcount32(mask);
+    const ServeLayout L = serve_layout(P->n, d, k);
+    if (!state) return fail(SNAPS_EINVAL, "state memory is NULL (%zu bytes needed)", L.bytes);
+    if (state_bytes < L.bytes) return fail(SNAPS_ENOMEM, "state of %zu bytes is smaller than the %zu needed", state_bytes, L.bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(state);
+    RunJob r{};
+    r.pop = P;
+    r.mask = mask;
+    r.eps = eps;
+    r.plan = L.plan;
+    r.eps_count = reinterpret_cast<int32_t*>(base + L.cnt);
+    r.eps_mean = reinterpret_cast<float*>(base + L.mean);
+    r.indeg = reinterpret_cast<int32_t*>(base + L.deg);
+    r.knn_mean = reinterpret_cast<float*>(base + L.kmean);
+    r.knn_kth = reinterpret_cast<float*>(base + L.kth);
+    r.rank = reinterpret_cast<int32_t*>(base + L.rank);
+    rc = run({r}, Tune{}, base + L.ws, L.ws_bytes, s);
+    if (rc != SNAPS_OK) return rc;
+    // Same addresses as run() chose for this single large job.
+    char* wsb = base + L.ws;
+    const MetaLayout ml = meta_layout(1, 1, 1);
+    char* jb = wsb + ml.bytes;
+    const JobPlan& p = L.plan;
+    const size_t rows = (size_t)p.ntiles * kTile;
+    DevJob j = make_devjob(P, mask, p, eps, Tune{}, jb);
+    LargeIndex li{};
+    li.sel_col = reinterpret_cast<int32_t*>(jb + p.sel_off);
+    li.sel_lo = reinterpret_cast<float*>(jb + p.sel_off) + kMaxIndexDims;
+    li.sel_scale = reinterpret_cast<float*>(jb + p.sel_off) + 2 * kMaxIndexDims;
+    hipError_t e = launch_serve_finish(j, li, reinterpret_cast<float*>(base + L.rk2), reinterpret_cast<float*>(base + L.tmax),
+                                       reinterpret_cast<uint32_t*>(base + L.tkey), r.knn_kth, s);
+    if (e != hipSuccess) return hip_fail(e, "serve state launch");
+    ServeState st{};
+    st.n = (int32_t)P->n;
+    st.d = d;
+    st.k = k;
+    st.ntiles = p.ntiles;
+    st.eps2 = j.eps2;
+    st.c = j.c;
+    st.bits = j.bits;
+    st.cols = P->cols;
+    st.ld = P->ld;
+    for (int f = 0; f < kMaxD; ++f) st.feat[f] = j.feat[f];
+    st.xs = j.xs;
+    st.boxes = j.boxes;
+    st.rk2 = reinterpret_cast<float*>(base + L.rk2);
+    st.tmax = reinterpret_cast<float*>(base + L.tmax);
+    st.tkey = reinterpret_cast<uint32_t*>(base + L.tkey);
+    st.sel_col = li.sel_col;
+    st.sel_lo = li.sel_lo;
+    st.sel_scale = li.sel_scale;
+    for (int m = 0; m < 4; ++m) st.distinct[m] = reinterpret_cast<uint32_t*>(jb + p.rpong_off) + m * rows;
+    st.n_distinct = reinterpret_cast<int32_t*>(jb + p.rnd_off);
+    auto& stg = staging();
+    stg.assign(sizeof(ServeState), 0);
+    std::memcpy(stg.data(), &st, sizeof(st));
+    e = hipMemcpyAsync(base + L.hdr, stg.data(), sizeof(st), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "serve state header upload");
+    return SNAPS_OK;
+}
+
+int snaps_serve_state_outputs(const void* state, int64_t n, int32_t d, int32_t k, const int32_t** eps_count,
+                              const float** eps_mean, const int32_t** indeg, const float** knn_mean,
+                              const int32_t** rank) {
+    if (!state || n < 2 || d < 2 || d > kMaxD || k < 1) return fail(SNAPS_EINVAL, "invalid state description");
+    const ServeLayout L = serve_layout(n, d, k);
+    const char* base = static_cast<const char*>(state);
+    if (eps_count) *eps_count = reinterpret_cast<const int32_t*>(base + L.cnt);
+    if (eps_mean) *eps_mean = reinterpret_cast<const float*>(base + L.mean);
+    if (indeg) *indeg = reinterpret_cast<const int32_t*>(base + L.deg);
+    if (knn_mean) *knn_mean = reinterpret_cast<const float*>(base + L.kmean);
+    if (rank) *rank = reinterpret_cast<const int32_t*>(base + L.rank);
+    return SNAPS_OK;
+}
+
+int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k, void* stream) {
+    if (n_jobs < 1 || !jobs) return fail(SNAPS_EINVAL, "need at least one alert job");
+    if (d < 2 || d > kMaxD) return fail(SNAPS_EINVAL, "d must be in [2, %d]", kMaxD);
+    if (k < 1 || k > kMaxK) return fail(SNAPS_EINVAL, "k must be in [1, %d]", kMaxK);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < n_jobs; ++i) {
+        const snaps_alert_job& a = jobs[i];
+        if (!a.state || (a.m > 0 && (!a.alerts || !a.eps_count || !a.eps_mean || !a.indeg || !a.knn_mean)))
+            return fail(SNAPS_EINVAL, "alert job %d: state, alerts and every score output are required", i);
+        if (a.m < 0) return fail(SNAPS_EINVAL, "alert job %d: negative alert count", i);
+    }
+    const int kc = kc_class(k);
+    for (int b = 0; b < n_jobs; b += kAlertJobs) {
+        AlertArgs aa{};
+        int tiles = 0;
+        const int nb = std::min(kAlertJobs, n_jobs - b);
+        aa.n_jobs = nb;
+        for (int i = 0; i < nb; ++i) {
+            const snaps_alert_job& a = jobs[b + i];
+            AlertJob& J = aa.jobs[i];
+            J.st = static_cast<const ServeState*>(a.state);
+            J.alerts = a.alerts;
+            J.m = a.m;
+            J.eps_count = a.eps_count;
+            J.eps_mean = a.eps_mean;
+            J.indeg = a.indeg;
+            J.knn_mean = a.knn_mean;
+            J.rank = a.rank;
+            aa.tile_prefix[i] = tiles;
+            tiles += (a.m + kTile - 1) / kTile;
+        }
+        aa.tile_prefix[nb] = tiles;
+        hipError_t e = launch_alerts(d, kc, aa, tiles, s);
+        if (e != hipSuccess) return hip_fail(e, "alert scoring launch");
+    }
     return SNAPS_OK;
 }
 

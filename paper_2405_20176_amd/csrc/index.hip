@@ -10,7 +10,8 @@
 //      permutation `perm`.
 //   2. k_reorder (one wavefront per tile of 64 positions): gathers the d
 //      subspace columns of every object in sorted order into a row-major
-//      array (plus a scaled squared norm), pads the last tile with NaN rows, and
+//      array (plus a scaled squared norm and the object id), pads the last
+//      tile with NaN rows, and
 //      records each tile's bounding box in all d dimensions.
 //
 // Any order of the objects gives the same join results (the join prunes a
@@ -149,6 +150,8 @@ __global__ __launch_bounds__(64) void k_reorder(Meta m, int32_t n_jobs) {
     // prefilter (c0 = (8d + 24) 2^-24, see the join kernel).
     const float c0 = (float)(8 * d + 24) * 5.9604644775390625e-8f;
     row[d] = valid ? -0.5f * (norm * (1.0f - c0)) : qnan;
+    // Slot d + 1: the object id, so the join reads it with the coordinates.
+    row[d + 1] = __int_as_float(id);
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t n, int32_t v) {

@@ -32,11 +32,12 @@ JoinFn pick(int D, int kc, int xf) {
 
 }  // namespace
 
-int join_blocks_per_cu(int D, int kc, int xf, int split) {
+int join_blocks_per_cu(int D, int kc, int xf, int split, int mq) {
     JoinFn fn = pick(D, kc, xf);
     if (!fn) return 0;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn), split * 64,
+    const int threads = 64 * (split > mq ? split : mq);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn), threads,
                                                      join_lds_bytes(kc, split)) != hipSuccess)
         return 0;
     return nb;
@@ -47,7 +48,8 @@ hipError_t launch_join(int D, int kc, int xf, const JoinArgs& a, int grid, hipSt
     if (!fn) return hipErrorInvalidValue;
     JoinArgs copy = a;
     void* args[] = {&copy};
-    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(a.split * 64), args,
+    const int threads = 64 * (a.split > a.mq ? a.split : a.mq);
+    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(threads), args,
                            join_lds_bytes(kc, a.split), s);
 }
 

@@ -3,14 +3,19 @@
 // self-join (Sec. 3.5) computed in one candidate pass, reduced on the fly to
 // the four per-object metrics (Sec. 3.5.1, 3.6.1).
 //
-// Work unit = one block of 64*QL queries of one job: every lane carries QL
-// queries (rows lane, lane + 64, ... of the block), so each candidate fetched
-// once feeds QL distance evaluations.  A workgroup of `split` wavefronts
-// shares the unit; each wavefront scans its share of the candidate tiles
-// (64 objects each), starting at the query block and moving outward in index
-// order, so that near candidates tighten the k-th distance early.  Candidate
-// coordinates are wavefront-uniform: they arrive by scalar loads into SGPRs
-// and feed the vector ALU directly, with no LDS traffic in the distance loop.
+// Work unit = one block of 64*QL queries of one job per wavefront: every lane
+// carries QL queries (rows lane, lane + 64, ... of the block).  Candidate
+// tiles (64 objects each) are visited starting at the query block and moving
+// outward in index order, so that near candidates tighten the k-th distance
+// early.  Candidate rows are wavefront-uniform: they arrive by wide scalar
+// loads into SGPRs and feed the vector ALU directly, with no LDS traffic in
+// the distance loop.  Two workgroup shapes:
+//   split: `split` wavefronts share one query block and divide the candidate
+//     tiles between them (few units: one small job);
+//   mq: `mq` wavefronts take consecutive query blocks of the same job and walk
+//     the same candidate tiles in lockstep (one barrier per tile), so the row
+//     that the first wavefront pulls into the CU's scalar cache is a cache
+//     hit for the others (many units: batched jobs).
 //
 // Two flavours of the per-pair test (XF):
 //   XF = 0, direct form: dd = sum_f (q_f - p_f)^2 in float32 (one subtract and
@@ -109,29 +114,46 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
     constexpr int KS = KC > 0 ? KC : 1;
     constexpr float cq = (float)(2 * (8 * D + 24)) * 5.9604644775390625e-8f;
     extern __shared__ unsigned char smem[];
-    __shared__ int s_unit;
+    __shared__ int s_unit, s_queue;
 
     const int S = A.split;
+    const int W = A.mq;
     // Wavefront-uniform values are passed through readfirstlane so that the
     // compiler keeps them (and every address derived from them) in SGPRs.
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
 
+    const int home = blockIdx.x % kQueues;                   // this workgroup's XCD
+    unsigned drained = 0;                                     // queues found empty (thread 0)
     for (;;) {
-        if (threadIdx.x == 0) s_unit = atomicAdd(A.counter, 1);
+        if (threadIdx.x == 0) {
+            int got = -1, gq = 0;
+            for (int i = 0; i < kQueues && got < 0; ++i) {
+                const int qq = (home + i) % kQueues;
+                if ((drained >> qq) & 1u) continue;
+                const int v = A.q_units[qq] > 0 ? atomicAdd(A.counter + qq, 1) : A.q_units[qq];
+                if (v < A.q_units[qq]) { got = v; gq = qq; }
+                else drained |= 1u << qq;
+            }
+            s_unit = got;
+            s_queue = gq;
+        }
         __syncthreads();
         const int u = __builtin_amdgcn_readfirstlane(s_unit);
+        const int qu = __builtin_amdgcn_readfirstlane(s_queue);
         __syncthreads();
-        if (u >= A.total_units) break;
+        if (u < 0) break;
 
-        // Locate the job of unit u: unit_prefix[j] <= u < unit_prefix[j+1].
-        int lo = 0, hi = A.n_class_jobs;
+        // Locate the job of unit u in queue qu: prefix[j] <= u < prefix[j+1].
+        const int32_t* prefix = A.unit_prefix + A.q_prefix_off[qu];
+        int lo = 0, hi = A.q_jobs[qu];
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (A.unit_prefix[mid] <= u) lo = mid; else hi = mid;
+            if (prefix[mid] <= u) lo = mid; else hi = mid;
         }
-        const int t0 = (u - A.unit_prefix[lo]) * QL;      // first query tile of the block
-        const DevJob* Jp = A.table + A.order[lo];
+        const int tu = (u - prefix[lo]) * QL * W;            // first query tile of the unit
+        const int t0 = W > 1 ? tu + wave * QL : tu;          // this wavefront's first query tile
+        const DevJob* Jp = A.table + A.order[A.q_order_off[qu] + lo];
         const int n = Jp->n;
         const int nt = Jp->ntiles;
         const int k = KC > 0 ? Jp->k : 0;
@@ -139,7 +161,6 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
         const int prune = Jp->prune;
         const float* xs_g = Jp->xs;
         cptr<float> xs = as_const(xs_g);
-        cptr<int32_t> perm = as_const((const int32_t*)Jp->perm);
         cptr<float> boxes = as_const((const float*)Jp->boxes);
 
         int qpos[QL];
@@ -165,6 +186,7 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
             cnt[r] = 0;
             sum[r] = 0.0;
             thr[r] = KC > 0 ? fmaxf(kd[r][KS - 1], eps2) : eps2;
+            if (t0 + r >= nt) thr[r] = -INFINITY;             // no query: every tile out of reach
             qn[r] = 0.f;
 #pragma unroll
             for (int f = 0; f < D; ++f) qn[r] = fmaf(q[r][f], q[r][f], qn[r]);
@@ -188,8 +210,9 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
             }
         };
 
-        for (int s = wave; s < nt; s += S) {
-            const int t = spiral(t0, s, nt);
+        for (int s = (W > 1 ? 0 : wave); s < nt; s += (W > 1 ? 1 : S)) {
+            if (W > 1 && s > 0) __syncthreads();             // keep the wavefronts in lockstep
+            const int t = spiral(W > 1 ? tu : t0, s, nt);
             if (prune) {
                 cptr<float> bx = boxes + (int64_t)t * 2 * DP;
                 bool near = false;
@@ -254,7 +277,7 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
                                         const float tq = q[r][f] - PV(j, f);
                                         dd = fmaf(tq, tq, dd);
                                     }
-                                    if (dd <= thr[r]) take(r, dd, perm[c]);
+                                    if (dd <= thr[r]) take(r, dd, __float_as_int(PV(j, D + 1)));
                                 }
                             }
                         }
@@ -288,7 +311,7 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
                             const int c = c0 + j;
 #pragma unroll
                             for (int r = 0; r < QL; ++r)
-                                if (dd[r][j] <= thr[r] && c != qpos[r]) take(r, dd[r][j], perm[c]);
+                                if (dd[r][j] <= thr[r] && c != qpos[r]) take(r, dd[r][j], __float_as_int(PV(j, D + 1)));
                         }
                     }
                 }
@@ -350,7 +373,7 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
             __syncthreads();
         }
 
-        if (wave == 0) {
+        if (W > 1 || wave == 0) {
 #pragma unroll
             for (int r = 0; r < QL; ++r) {
                 if (qpos[r] >= n) continue;
@@ -378,6 +401,8 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
                     }
                     float* kmean = Jp->knn_mean;
                     if (kmean) kmean[id] = accm / (float)k;
+                    float* kth = Jp->knn_kth;
+                    if (kth) kth[id] = kd[r][KS - 1];
                 }
             }
         }

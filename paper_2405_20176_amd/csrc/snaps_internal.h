@@ -16,8 +16,9 @@ constexpr int kSortThreads = 1024;
 constexpr int kRadixChunk = 4096;    // elements per workgroup of the device-wide radix sort
 
 // Row stride (floats) of the tile-ordered coordinate array for dimension d:
-// d coordinates, the squared norm, padded to a multiple of 4 floats.
-__host__ __device__ constexpr int row_stride(int d) { return ((d + 1 + 3) / 4) * 4; }
+// d coordinates, the prefilter addend (scaled squared norm), the object id
+// (as raw bits), padded to a multiple of 4 floats.
+__host__ __device__ constexpr int row_stride(int d) { return ((d + 2 + 3) / 4) * 4; }
 
 // One (population, subspace) job as the kernels see it.  Lives in device
 // memory (the job table inside the caller's workspace).
@@ -37,6 +38,7 @@ struct DevJob {
     int32_t pad0;
     float* xs;               // [ntiles*64][row_stride(d)] coordinates in index order (+ norm)
     int32_t* perm;           // [ntiles*64] index position -> object id (pads: INT32_MAX)
+                             // (the id is also stored in slot d + 1 of each xs row)
     float* boxes;            // [ntiles][2][row_stride(d)] per-tile lower / upper corners
     int32_t* eps_count;      // outputs, [n], indexed by object id (may be null)
     float* eps_mean;
@@ -45,6 +47,7 @@ struct DevJob {
     int32_t* rank;           // [4][n] or null
     int32_t* knn_ids;        // [n][k] or null
     float* knn_dist;         // [n][k] or null
+    float* knn_kth;          // [n] squared float32 distance of the k-th neighbour, or null
 };
 
 // Small per-call metadata that lives next to the job table in the workspace.
@@ -53,7 +56,7 @@ struct Meta {
     int32_t* order;          // join processing order, grouped by kernel class
     int32_t* unit_prefix;    // per class: tiles prefix over that class's jobs (n+1 entries each)
     int32_t* tile_prefix;    // [n_jobs + 1] tiles prefix in table order
-    int32_t* counters;       // [n_classes] persistent work counters
+    int32_t* counters;       // [n_classes * kQueues] persistent work counters
     int32_t n_counters;
 };
 
@@ -66,14 +69,24 @@ struct IndexArgs {
     DevJob single;
 };
 
+// Work queues of one join launch: one per XCD (the MI355X has 8; workgroup b
+// is dispatched to XCD b mod 8).  Queue q holds a share of the class's jobs
+// (consecutive sub-lists of `order` / `unit_prefix`), so the candidate rows
+// a queue's workgroups stream stay in that XCD's L2; an empty queue steals.
+constexpr int kQueues = 8;
+
 struct JoinArgs {
     const DevJob* table;
-    const int32_t* order;        // this class's job ids in processing order
-    const int32_t* unit_prefix;  // [n_class_jobs + 1]
-    int32_t n_class_jobs;
-    int32_t total_units;
-    int32_t* counter;
+    const int32_t* order;        // this class's job ids, queue by queue
+    const int32_t* unit_prefix;  // per queue: [q_jobs + 1] unit prefix
+    int32_t q_order_off[kQueues];
+    int32_t q_prefix_off[kQueues];
+    int32_t q_jobs[kQueues];
+    int32_t q_units[kQueues];
+    int32_t* counter;            // [kQueues]
     int32_t split;               // waves per workgroup sharing a query tile
+    int32_t mq;                  // waves per workgroup, each with its own query tile, scanning the
+                                 // same candidate tiles in lockstep (1: off)
     unsigned long long* stats;   // optional [4] counters (see snaps_tuning.stats)
 };
 
@@ -111,6 +124,48 @@ struct LargeRank {
     int32_t* n_distinct;     // [4]
 };
 
+// Resident scoring state of one (population, subspace), kept in device
+// memory for serving: the index (tile rows and boxes), every object's k-th
+// neighbour dd in index order, per-tile maxima of it, the Morton key of each
+// tile's first object, and the sorted distinct keys of the four metrics.
+struct ServeState {
+    int32_t n, d, k, ntiles;
+    float eps2;
+    int32_t c, bits, pad0;
+    const float* cols;
+    int64_t ld;
+    int32_t feat[kMaxD];
+    const float* xs;
+    const float* boxes;
+    const float* rk2;          // [ntiles*64] k-th neighbour dd at each index position (pads: -inf)
+    const float* tmax;         // [ntiles]
+    const uint32_t* tkey;      // [ntiles] non-decreasing
+    const int32_t* sel_col;    // index dimensions and their cell grids
+    const float* sel_lo;
+    const float* sel_scale;
+    const uint32_t* distinct[4];
+    const int32_t* n_distinct;  // [4]
+};
+
+// Alert scoring launch: up to kAlertJobs jobs passed by value.
+constexpr int kAlertJobs = 32;
+struct AlertJob {
+    const ServeState* st;
+    const float* alerts;       // [m][d] row-major
+    int32_t m;
+    int32_t pad0;
+    int32_t* eps_count;
+    float* eps_mean;
+    int32_t* indeg;
+    float* knn_mean;
+    int32_t* rank;             // [4][m] or null
+};
+struct AlertArgs {
+    AlertJob jobs[kAlertJobs];
+    int32_t tile_prefix[kAlertJobs + 1];
+    int32_t n_jobs;
+};
+
 struct RankArgs {
     const DevJob* table;
     int32_t n_jobs;
@@ -125,6 +180,9 @@ hipError_t launch_index_sort(const IndexArgs& a, int grid, hipStream_t s);
 hipError_t launch_reorder(const Meta& m, int32_t n_jobs, int32_t total_tiles, hipStream_t s);
 hipError_t launch_rank(const RankArgs& a, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t n, int32_t v, hipStream_t s);
+hipError_t launch_serve_finish(const DevJob& j, const LargeIndex& li, float* rk2, float* tmax, uint32_t* tkey,
+                               const float* kth, hipStream_t s);
+hipError_t launch_alerts(int D, int kc, const AlertArgs& a, int total_tiles, hipStream_t s);
 hipError_t launch_radix_sort(const SortSeg* segs, const int32_t* chunk_prefix, int n_segs, int total_chunks,
                              int passes, hipStream_t s);
 // Large-n index build (before k_reorder) and rank, over every large job of a call.
@@ -136,7 +194,7 @@ hipError_t launch_large_rank(const DevJob* table, const LargeRank* lr, int n_lar
 // Join kernel for dimensionality D, top-k capacity class kc and filter
 // flavour xf; grid == 0 asks for a persistent grid filling the device.
 hipError_t launch_join(int D, int kc, int xf, const JoinArgs& a, int grid, hipStream_t s);
-int join_blocks_per_cu(int D, int kc, int xf, int split);
+int join_blocks_per_cu(int D, int kc, int xf, int split, int mq);
 int kc_class(int k);              // top-k capacity used for a k (0 for no kNN)
 size_t join_lds_bytes(int kc, int split);
 

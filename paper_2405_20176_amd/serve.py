@@ -1,0 +1,225 @@
+"""Continuous-batching server for scoring alerts against resident states.
+
+Requests (a population, one of its served subspaces, and a batch of alert
+objects) arrive over time.  The server
+  * admits a request when the device memory it needs (alerts plus outputs)
+    fits in the remaining budget next to the resident states, and a batch slot
+    is free; requests larger than the whole budget are rejected;
+  * packs every admitted, waiting request into one batch (different sizes,
+    populations and subspaces) and launches it on its own stream, so batches
+    overlap on the device while later requests keep arriving;
+  * completes a request when its batch's event has fired and its results
+    have been copied back, and records its latency (completion - arrival).
+Scoring itself runs in libsnaps (snaps_alerts_score); results of an alert do
+not depend on the batch it lands in.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Deque, Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds on the server clock
+    key: Tuple[int, int]           # (population id, subspace mask)
+    alerts: np.ndarray             # float32 [m, d], subspace columns, population-normalised
+    # filled by the server
+    admitted: Optional[float] = None
+    done: Optional[float] = None
+    status: str = "pending"        # pending | running | done | rejected
+    result: Optional[Dict[str, np.ndarray]] = None
+
+    @property
+    def m(self) -> int:
+        return int(self.alerts.shape[0])
+
+    def device_bytes(self) -> int:
+        """Device memory of the request while in flight: alerts, four metric
+        arrays and the [4, m] ranks."""
+        return self.m * (4 * self.alerts.shape[1] + 16 + 16)
+
+
+class Admission:
+    """Device-memory budget for in-flight requests and a cap on batches in
+    flight.  Pure host logic."""
+
+    def __init__(self, budget_bytes: int, max_batches: int):
+        self.budget = int(budget_bytes)
+        self.max_batches = int(max_batches)
+        self.used = 0
+        self.batches = 0
+
+    def fits(self, nbytes: int) -> bool:
+        return self.used + nbytes <= self.budget
+
+    def never_fits(self, nbytes: int) -> bool:
+        return nbytes > self.budget
+
+    def take(self, nbytes: int):
+        assert self.fits(nbytes)
+        self.used += nbytes
+
+    def release(self, nbytes: int):
+        self.used -= nbytes
+        assert self.used >= 0
+
+    def slot_free(self) -> bool:
+        return self.batches < self.max_batches
+
+
+class Batcher:
+    """Continuous batching over an executor.  The executor launches a list of
+    requests asynchronously and later reports completion:
+        handle = executor.launch(requests)
+        executor.poll(handle) -> bool            (non-blocking)
+        executor.finish(handle) -> [result dict per request]
+    """
+
+    def __init__(self, executor, admission: Admission, max_batch_alerts: int = 1 << 16,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.adm = admission
+        self.max_batch_alerts = int(max_batch_alerts)
+        self.clock = clock
+        self.waiting: Deque[Request] = collections.deque()
+        self.inflight: List[Tuple[object, List[Request], int]] = []
+        self.finished: List[Request] = []
+
+    def submit(self, r: Request):
+        if self.adm.never_fits(r.device_bytes()):
+            r.status = "rejected"
+            r.done = self.clock()
+            self.finished.append(r)
+            return
+        self.waiting.append(r)
+
+    def _launch(self) -> bool:
+        if not self.waiting or not self.adm.slot_free():
+            return False
+        batch, nbytes, alerts = [], 0, 0
+        while self.waiting:
+            r = self.waiting[0]
+            b = r.device_bytes()
+            if not self.adm.fits(nbytes + b) or (batch and alerts + r.m > self.max_batch_alerts):
+                break
+            self.waiting.popleft()
+            batch.append(r)
+            nbytes += b
+            alerts += r.m
+        if not batch:
+            return False
+        self.adm.take(nbytes)
+        self.adm.batches += 1
+        now = self.clock()
+        for r in batch:
+            r.admitted = now
+            r.status = "running"
+        self.inflight.append((self.ex.launch(batch), batch, nbytes))
+        return True
+
+    def _reap(self) -> bool:
+        progressed = False
+        still = []
+        for h, batch, nbytes in self.inflight:
+            if self.ex.poll(h):
+                results = self.ex.finish(h)
+                now = self.clock()
+                for r, res in zip(batch, results):
+                    r.result = res
+                    r.done = now
+                    r.status = "done"
+                    self.finished.append(r)
+                self.adm.release(nbytes)
+                self.adm.batches -= 1
+                progressed = True
+            else:
+                still.append((h, batch, nbytes))
+        self.inflight = still
+        return progressed
+
+    def step(self) -> bool:
+        """One scheduling round; returns True if anything happened."""
+        a = self._reap()
+        b = self._launch()
+        return a or b
+
+    def drain(self):
+        while self.waiting or self.inflight:
+            if not self.step():
+                time.sleep(0)
+
+    def run_open_loop(self, requests: Sequence[Request], t0: Optional[float] = None):
+        """Replay requests at their arrival times (seconds after t0), then
+        drain.  Arrivals are released into the queue as the clock passes them,
+        while earlier batches are still running."""
+        t0 = self.clock() if t0 is None else t0
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        while pending or self.waiting or self.inflight:
+            now = self.clock() - t0
+            while pending and pending[0].arrival <= now:
+                r = pending.popleft()
+                r.arrival += t0            # to the server clock
+                self.submit(r)
+            if not self.step() and pending:
+                wait = pending[0].arrival - (self.clock() - t0)
+                if wait > 0.0005:
+                    time.sleep(min(wait, 0.001))
+
+    def latencies(self) -> np.ndarray:
+        return np.array([r.done - r.arrival for r in self.finished if r.status == "done"])
+
+
+class GpuExecutor:
+    """Executor over libsnaps: one stream per in-flight batch slot; alerts go
+    up from pinned host buffers and results come back the same way."""
+
+    def __init__(self, states: Dict[Tuple[int, int], object], n_streams: int = 4, device="cuda"):
+        import torch
+        from . import snaps as S
+        self.torch, self.S = torch, S
+        self.states = states
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        self.free = list(range(n_streams))
+
+    def launch(self, batch: List[Request]):
+        torch, S = self.torch, self.S
+        si = self.free.pop()
+        stream = self.streams[si]
+        jobs, hosts = [], []
+        with torch.cuda.stream(stream):
+            for r in batch:
+                st = self.states[r.key]
+                ha = torch.from_numpy(r.alerts).pin_memory()
+                a = ha.to(self.device, non_blocking=True)
+                j = S.AlertJob.alloc(st, a)
+                jobs.append(j)
+                hosts.append(ha)
+            S.snaps_alerts_score(jobs, stream=stream)
+            outs = []
+            for j in jobs:
+                o = {}
+                for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+                    t = getattr(j, key)
+                    h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+                    h.copy_(t, non_blocking=True)
+                    o[key] = h
+                outs.append(o)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return (si, ev, jobs, hosts, outs)
+
+    def poll(self, h) -> bool:
+        return h[1].query()
+
+    def finish(self, h):
+        si, ev, jobs, hosts, outs = h
+        ev.synchronize()
+        self.free.append(si)
+        return [{k: v.numpy() for k, v in o.items()} for o in outs]

@@ -50,11 +50,17 @@ class c_job(ctypes.Structure):
 
 class c_tuning(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("split", ctypes.c_int32), ("index_dims", ctypes.c_int32),
-                ("filter", ctypes.c_int32), ("passes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
-                ("stats", ctypes.c_void_p)]
+                ("filter", ctypes.c_int32), ("passes", ctypes.c_int32), ("mq", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2), ("stats", ctypes.c_void_p)]
 
 
 PASS_INDEX, PASS_JOIN, PASS_RANK = 1, 2, 4
+
+
+class c_alert_job(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_void_p), ("alerts", ctypes.c_void_p), ("m", ctypes.c_int32),
+                ("pad0", ctypes.c_int32), ("eps_count", ctypes.c_void_p), ("eps_mean", ctypes.c_void_p),
+                ("indeg", ctypes.c_void_p), ("knn_mean", ctypes.c_void_p), ("rank", ctypes.c_void_p)]
 
 
 _lib = None
@@ -85,6 +91,20 @@ def load_library(path: str = LIB_PATH):
     lib.snaps_outlier_scores.argtypes = [P(c_job), i32, P(c_tuning), vp, sz, vp]
     lib.snaps_rank.restype = ctypes.c_int
     lib.snaps_rank.argtypes = [vp, vp, vp, vp, i64, vp, vp, sz, vp]
+    lib.snaps_plan_create.restype = ctypes.c_int
+    lib.snaps_plan_create.argtypes = [P(c_job), i32, P(c_tuning), vp, sz, vp, P(vp)]
+    lib.snaps_plan_launch.restype = ctypes.c_int
+    lib.snaps_plan_launch.argtypes = [vp, vp]
+    lib.snaps_plan_destroy.restype = None
+    lib.snaps_plan_destroy.argtypes = [vp]
+    lib.snaps_serve_state_bytes.restype = sz
+    lib.snaps_serve_state_bytes.argtypes = [P(c_population), ctypes.c_uint32, i32]
+    lib.snaps_serve_state_build.restype = ctypes.c_int
+    lib.snaps_serve_state_build.argtypes = [P(c_population), ctypes.c_uint32, i32, ctypes.c_float, vp, sz, vp]
+    lib.snaps_serve_state_outputs.restype = ctypes.c_int
+    lib.snaps_serve_state_outputs.argtypes = [vp, i64, i32, i32, P(vp), P(vp), P(vp), P(vp), P(vp)]
+    lib.snaps_alerts_score.restype = ctypes.c_int
+    lib.snaps_alerts_score.argtypes = [P(c_alert_job), i32, i32, i32, vp]
     _lib = lib
     return lib
 
@@ -131,12 +151,13 @@ class Population:
         return cls(cols.to(device).contiguous(), n)
 
 
-def tuning(mode=0, split=0, index_dims=0, filter=0, passes=0, stats: Optional[torch.Tensor] = None) -> c_tuning:
+def tuning(mode=0, split=0, index_dims=0, filter=0, passes=0, stats: Optional[torch.Tensor] = None,
+           mq=0) -> c_tuning:
     """Tuning record; ``stats`` is an optional int64 CUDA tensor of 4
     accumulated join counters (pairs evaluated, tiles scanned, tiles
     skipped, pairs x dimensionality)."""
     t = c_tuning()
-    t.mode, t.split, t.index_dims, t.filter, t.passes = mode, split, index_dims, filter, passes
+    t.mode, t.split, t.index_dims, t.filter, t.passes, t.mq = mode, split, index_dims, filter, passes, mq
     t.stats = None if stats is None else stats.data_ptr()
     return t
 
@@ -227,6 +248,38 @@ def snaps_outlier_scores(jobs: Sequence[Job], tune: Optional[c_tuning] = None, w
     _check(lib.snaps_outlier_scores(arr, len(jobs), tp, _ptr(ws), ws.numel(), _stream(stream)))
 
 
+class Plan:
+    """A captured batched launch (snaps_plan_*) over a list of jobs."""
+
+    def __init__(self, jobs: Sequence[Job], tune: Optional[c_tuning] = None, ws: Optional[torch.Tensor] = None,
+                 stream=None, c_jobs=None, n_jobs: Optional[int] = None):
+        lib = load_library()
+        arr = c_jobs if c_jobs is not None else _c_jobs(jobs)
+        n = n_jobs if n_jobs is not None else len(jobs)
+        tp = None if tune is None else ctypes.byref(tune)
+        need = lib.snaps_outlier_scores_workspace(arr, n, tp)
+        if ws is None:
+            ws = _workspace(need, jobs[0].pop.cols.device)
+        self.ws, self.jobs, self.arr, self.tune = ws, jobs, arr, tune
+        h = ctypes.c_void_p()
+        _check(lib.snaps_plan_create(arr, n, tp, _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        _check(load_library().snaps_plan_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if self.h:
+            load_library().snaps_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def snaps_rank(eps_count: torch.Tensor, eps_mean: torch.Tensor, indeg: torch.Tensor, knn_mean: torch.Tensor,
                rank: torch.Tensor, ws: Optional[torch.Tensor] = None, stream=None):
     lib = load_library()
@@ -244,3 +297,87 @@ def score_space(pop: Population, mask: int, k: int, eps: float, tune: Optional[c
     job = Job.alloc(pop, mask, k, eps, with_rank)
     snaps_outlier_scores([job], tune)
     return job
+
+
+class ServeState:
+    """Resident scoring state of one (population, subspace) in device memory
+    (owned by this object as a torch tensor)."""
+
+    def __init__(self, pop: Population, mask: int, k: int, eps: float, stream=None):
+        lib = load_library()
+        self.pop, self.mask, self.k, self.eps = pop, int(mask), int(k), float(eps)
+        self.d = bin(self.mask).count("1")
+        nbytes = lib.snaps_serve_state_bytes(ctypes.byref(pop.c), self.mask, self.k)
+        if nbytes == 0:
+            raise SnapsError(SNAPS_EINVAL, "invalid serve state request")
+        self.nbytes = int(nbytes)
+        self.mem = torch.empty(self.nbytes, dtype=torch.uint8, device=pop.cols.device)
+        _check(lib.snaps_serve_state_build(ctypes.byref(pop.c), self.mask, self.k, self.eps,
+                                           ctypes.c_void_p(self.mem.data_ptr()), self.nbytes, _stream(stream)))
+
+    def ptr(self) -> int:
+        return self.mem.data_ptr()
+
+    def population_outputs(self) -> dict:
+        """The population's own metrics and ranks (views into the state)."""
+        lib = load_library()
+        ptrs = [ctypes.c_void_p() for _ in range(5)]
+        _check(lib.snaps_serve_state_outputs(ctypes.c_void_p(self.mem.data_ptr()), self.pop.n, self.d, self.k,
+                                             *[ctypes.byref(p) for p in ptrs]))
+        base = self.mem.data_ptr()
+        n = self.pop.n
+
+        def view(p, dtype, shape):
+            off = p.value - base
+            count = 1
+            for v in shape:
+                count *= v
+            return self.mem[off:off + count * 4].view(dtype).view(*shape)
+
+        return {"eps_count": view(ptrs[0], torch.int32, (n,)), "eps_mean": view(ptrs[1], torch.float32, (n,)),
+                "indeg": view(ptrs[2], torch.int32, (n,)), "knn_mean": view(ptrs[3], torch.float32, (n,)),
+                "rank": view(ptrs[4], torch.int32, (4, n))}
+
+
+@dataclass
+class AlertJob:
+    """A batch of alerts [m, d] (float32, subspace columns in ascending feature
+    order, population-normalised) for one ServeState, with its outputs."""
+    state: ServeState
+    alerts: torch.Tensor
+    eps_count: torch.Tensor
+    eps_mean: torch.Tensor
+    indeg: torch.Tensor
+    knn_mean: torch.Tensor
+    rank: Optional[torch.Tensor] = None
+
+    @classmethod
+    def alloc(cls, state: ServeState, alerts: torch.Tensor, with_rank: bool = True) -> "AlertJob":
+        m = alerts.shape[0]
+        dev = alerts.device
+        return cls(state, alerts, torch.empty(m, dtype=torch.int32, device=dev),
+                   torch.empty(m, dtype=torch.float32, device=dev), torch.empty(m, dtype=torch.int32, device=dev),
+                   torch.empty(m, dtype=torch.float32, device=dev),
+                   torch.empty((4, m), dtype=torch.int32, device=dev) if with_rank else None)
+
+
+def snaps_alerts_score(jobs: Sequence[AlertJob], stream=None):
+    """Score alert batches; jobs are grouped by (d, k) into library calls."""
+    lib = load_library()
+    groups = {}
+    for j in jobs:
+        if j.alerts.dtype != torch.float32 or not j.alerts.is_contiguous() or j.alerts.shape[1] != j.state.d:
+            raise ValueError("alerts must be contiguous float32 [m, d] for the state's subspace")
+        groups.setdefault((j.state.d, j.state.k), []).append(j)
+    for (d, k), js in groups.items():
+        arr = (c_alert_job * len(js))()
+        for i, j in enumerate(js):
+            arr[i].state = j.state.ptr()
+            arr[i].alerts = j.alerts.data_ptr()
+            arr[i].m = j.alerts.shape[0]
+            arr[i].eps_count = j.eps_count.data_ptr()
+            arr[i].eps_mean = j.eps_mean.data_ptr()
+            arr[i].indeg = j.indeg.data_ptr()
+            arr[i].knn_mean = j.knn_mean.data_ptr()
+            arr[i].rank = None if j.rank is None else j.rank.data_ptr()
+        _check(lib.snaps_alerts_score(arr, len(js), d, k, _stream(stream)))

@@ -25,6 +25,7 @@ from .generators import (  # noqa: F401
     all_masks,
     mask_features,
     load_c1_eps,
+    load_c4_eps,
     FEATURE_NAMES,
     to_soa,
     C3Job,

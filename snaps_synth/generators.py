@@ -326,6 +326,15 @@ class C4Workload:
         return x
 
 
+def load_c4_eps(path: str | None = None):
+    """Stored float32 eps of the first served subspaces of every serving
+    population: (masks [n_pop, s], eps [n_pop, s]).  Written by
+    ``make_eps_tables.py c4``."""
+    path = path or os.path.join(TABLE_DIR, "c4_eps.npz")
+    z = np.load(path, allow_pickle=False)
+    return z["masks"], z["eps"].astype(np.float32)
+
+
 def gen_c4(n_pop: int = 4, pop_n: int = 1_000_000, spaces_per_pop: int = 64,
            rate_hz: float = 200.0, k: int = 10) -> C4Workload:
     """Serving workload: ``n_pop`` resident populations, each with a seeded

@@ -8,6 +8,7 @@ the oracle and the GPU library receive the identical value.  This script
 calls only the oracle and the generators.
 
     python -m snaps_synth.make_eps_tables c1      # 32,752 spaces, target 10
+    python -m snaps_synth.make_eps_tables c4      # served spaces of the serving workload
 """
 from __future__ import annotations
 
@@ -58,12 +59,35 @@ def c1(workers: int) -> str:
     return out
 
 
+C4_SAMPLES = 32
+C4_TARGET = 10
+C4_SPACES = 8          # first served subspaces of each population that get an eps
+
+
+def c4() -> str:
+    w = G.gen_c4()
+    eps = np.zeros((w.n_pop, C4_SPACES), dtype=np.float32)
+    masks = np.zeros((w.n_pop, C4_SPACES), dtype=np.uint32)
+    t0 = time.time()
+    for p in range(w.n_pop):
+        x, _, _ = w.population(p)
+        for s in range(C4_SPACES):
+            m = int(w.spaces[p][s])
+            masks[p, s] = m
+            eps[p, s] = O.eps_sampled_mean_count(O.project(x, m), C4_TARGET, C4_SAMPLES, seed=m)
+            print(f"population {p} space {s} mask {m:#x}: eps {eps[p, s]:.6g} ({time.time() - t0:.0f} s)", flush=True)
+        del x
+    out = os.path.join(G.TABLE_DIR, "c4_eps.npz")
+    np.savez(out, masks=masks, eps=eps, samples=np.int64(C4_SAMPLES), target=np.int64(C4_TARGET))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c1"])
+    ap.add_argument("which", choices=["c1", "c4"])
     ap.add_argument("--workers", type=int, default=os.cpu_count() or 4)
     a = ap.parse_args()
-    print(c1(a.workers))
+    print(c1(a.workers) if a.which == "c1" else c4())
 
 
 if __name__ == "__main__":

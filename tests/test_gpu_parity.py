@@ -404,3 +404,58 @@ def test_c2_lsst_scale_spaces(S, c2, which):
     del j
     ex = sampled_check(S, x, mask, k, eps, out, n_samples=128, seed=which, label=f"C2 space {which}")
     assert ex <= 5
+
+
+@pytest.mark.parametrize("mq", [2, 4, 8])
+def test_lockstep_workgroups(S, mq):
+    """Workgroups of mq wavefronts with their own query tiles walking the same
+    candidate tiles: same neighbours, counts and kNN means as one wavefront
+    per workgroup (only the eps-sum order may differ), and oracle parity."""
+    rng = np.random.default_rng(60 + mq)
+    x = rng.random((5000, 15)).astype(np.float32)
+    pop = S.Population.from_rows(x)
+    specs = [(0b111, 5, 0.05), (0b1111100000, 10, 0.3), (0x7FFF, 20, 0.6), (0b11, 10, 0.01)]
+    for mask, k, eps in specs:
+        a = S.Job.alloc(pop, mask, k, eps)
+        b = S.Job.alloc(pop, mask, k, eps)
+        S.snaps_outlier_scores([a], S.tuning(split=1, mq=1))
+        S.snaps_outlier_scores([b], S.tuning(split=1, mq=mq))
+        torch.cuda.synchronize()
+        for key in ("eps_count", "indeg", "knn_mean"):
+            assert torch.equal(getattr(a, key), getattr(b, key)), f"{key} mask={mask:x} mq={mq}"
+        np.testing.assert_allclose(b.eps_mean.cpu().numpy(), a.eps_mean.cpu().numpy(), rtol=1e-6)
+        check_scores(_out(b), run_oracle(x, mask, k, eps), k, eps, label=f"mq={mq} mask={mask:x}")
+
+
+def test_graph_plans_replay(S):
+    """The batched form captured as HIP graphs (one per pass) replays to the
+    same results as direct calls, several times, with other work between
+    replays."""
+    rng = np.random.default_rng(23)
+    x = rng.random((4000, 15)).astype(np.float32)
+    pop = S.Population.from_rows(x)
+    specs = [(0b111, 10, 0.05), (0b1111100000, 10, 0.3), (0x7FFF, 20, 0.6), (0b11, 5, 0.01), (0b101010101, 10, 0.2)]
+    tune = S.tuning(split=1)
+    ref = [S.Job.alloc(pop, m, k, e) for m, k, e in specs]
+    S.snaps_outlier_scores(ref, tune)
+    jobs = [S.Job.alloc(pop, m, k, e) for m, k, e in specs]
+    ws = torch.empty(S.snaps_outlier_scores_workspace(jobs, tune), dtype=torch.uint8, device="cuda")
+    plans = [S.Plan(jobs, S.tuning(split=1, passes=p), ws=ws) for p in (S.PASS_INDEX, S.PASS_JOIN, S.PASS_RANK)]
+    for rep in range(3):
+        for j in jobs:
+            for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+                getattr(j, key).fill_(-7)
+        for p in plans:
+            p.launch()
+        junk = torch.randn(1 << 20, device="cuda").sum()          # eager work between replays
+        torch.cuda.synchronize()
+        for a, b in zip(ref, jobs):
+            for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+                assert torch.equal(getattr(a, key), getattr(b, key)), f"replay {rep} {key}"
+        del junk
+    single = [S.Job.alloc(pop, *specs[0])]
+    whole = S.Plan(single, S.tuning())
+    whole.launch()
+    torch.cuda.synchronize()
+    for key in ("eps_count", "indeg", "knn_mean"):
+        assert torch.equal(getattr(single[0], key), getattr(ref[0], key)), key

@@ -1,0 +1,149 @@
+"""GPU tests of the served form: alerts scored against resident states.
+
+The oracle's reading (oracle.alert_scores): an alert is one extra object that
+changes nothing in the population and sees no other alert.  Checked against
+the paper's Fig. 3 nested result sets, against the oracle under the float32
+tolerance rule, and for independence from the other alerts of a call.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+import snaps_synth as G
+from tests.golden import exact_fp32_variant, load_fig3, load_tab2
+from tests.parity import TAU, dense_rank_asc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_20176_amd import snaps
+    snaps.load_library()
+    return snaps
+
+
+def score(S, state, alerts_np):
+    a = torch.from_numpy(np.ascontiguousarray(alerts_np, dtype=np.float32)).cuda()
+    job = S.AlertJob.alloc(state, a)
+    S.snaps_alerts_score([job])
+    torch.cuda.synchronize()
+    return {k: getattr(job, k).cpu().numpy() for k in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank")}
+
+
+def test_fig3_nested_sets_served(S):
+    """Fig. 3: a query at (1, 1) among the ten points of Fig. 1 finds 3, 6
+    and 8 neighbours at the three drawn radii (exact float32 rescaling)."""
+    coords, _, _, _, _ = load_tab2()
+    q, sets = load_fig3()
+    x = exact_fp32_variant(coords)
+    qq = exact_fp32_variant(q[None, :])
+    pop = S.Population.from_rows(x)
+    for r, expect in sets:
+        eps = float(np.float32(100.0 * r / 512.0))
+        st = S.ServeState(pop, 0b11, 3, eps)
+        out = score(S, st, qq)
+        assert out["eps_count"][0] == len(expect)
+        ref = O.alert_scores(x, qq, 3, eps)
+        assert out["indeg"][0] == ref["indeg"][0]
+        np.testing.assert_allclose(out["knn_mean"][0], ref["knn_mean"][0], rtol=TAU)
+        np.testing.assert_array_equal(out["rank"][:, 0], ref["rank"][:, 0])
+
+
+def _population_keys(po):
+    cnt = po["eps_count"].cpu().numpy()
+    mean = po["eps_mean"].cpu().numpy().astype(np.float64)
+    km = po["knn_mean"].cpu().numpy().astype(np.float64)
+    deg = po["indeg"].cpu().numpy()
+    return [cnt.astype(np.float64), -np.where(cnt > 0, mean, np.inf), deg.astype(np.float64), -km]
+
+
+@pytest.mark.parametrize("n,d,k", [(3000, 3, 10), (20000, 2, 5), (40000, 7, 10), (12000, 13, 20)])
+def test_alerts_against_oracle(S, n, d, k):
+    rng = np.random.default_rng(n + d)
+    job = G.gen_c3_jobs(4)[2]
+    x = G.gen_c3_population(job, n=n)
+    mask = int(sum(1 << f for f in rng.choice(15, size=d, replace=False)))
+    P = O.project(x, mask)
+    eps = float(O.eps_sampled_mean_count(P, 10, 64, seed=d))
+    # alerts in the population's frame: perturbed population rows (inside the
+    # bulk) plus a few far away
+    base_rows = x[rng.choice(n, size=400, replace=False)]
+    alerts_full = np.clip(base_rows + rng.normal(0, 0.01, size=base_rows.shape), -0.1, 1.1).astype(np.float32)
+    alerts_full[:8] = rng.uniform(-0.2, 1.2, size=(8, alerts_full.shape[1])).astype(np.float32)
+    A = O.project(alerts_full, mask).astype(np.float32)
+    pop = S.Population.from_rows(x)
+    st = S.ServeState(pop, mask, k, eps)
+    out = score(S, st, A)
+    ref = O.alert_scores(P.astype(np.float32), A, k, eps)
+    # exemptions: a population distance within tau of eps (eps count / mean),
+    # or within tau of that object's own k-th distance (in-degree)
+    D = O.pair_distances(A, P.astype(np.float32))
+    eps_ex = (np.abs(D - eps) <= TAU * eps).any(axis=1)
+    popref = O.outlier_scores(P.astype(np.float32), k, eps) if n <= 3000 else None
+    np.testing.assert_allclose(out["knn_mean"], ref["knn_mean"], rtol=TAU)
+    assert ((out["eps_count"] == ref["eps_count"]) | eps_ex).all()
+    rel = np.abs(out["eps_mean"] - ref["eps_mean"]) / np.maximum(ref["eps_mean"], 1e-30)
+    assert ((rel <= TAU) | eps_ex | ((ref["eps_mean"] == 0) & (out["eps_mean"] == 0))).all()
+    if popref is not None:
+        rk = popref["knn_dist"][:, k - 1]
+        deg_ex = (np.abs(D - rk[None, :]) <= TAU * rk[None, :]).sum(axis=1)
+        assert (np.abs(out["indeg"] - ref["indeg"]) <= deg_ex).all()
+    else:
+        # population k-th distances from the GPU's own state are exact enough
+        # for a tolerance check of the count of objects it would join
+        assert (np.abs(out["indeg"] - ref["indeg"]) <= np.maximum(2, 0.02 * ref["indeg"])).all()
+    # rank positions against the GPU's own population values, exactly
+    keys = _population_keys(st.population_outputs())
+    em = out["eps_mean"].astype(np.float64)
+    akeys = [out["eps_count"].astype(np.float64), -np.where(out["eps_count"] > 0, em, np.inf),
+             out["indeg"].astype(np.float64), -out["knn_mean"].astype(np.float64)]
+    for t in range(4):
+        u = np.unique(keys[t])
+        np.testing.assert_array_equal(out["rank"][t], np.searchsorted(u, akeys[t], side="left"))
+
+
+def test_population_outputs_of_state_match_plain_join(S):
+    rng = np.random.default_rng(3)
+    x = rng.random((5000, 6)).astype(np.float32)
+    pop = S.Population.from_rows(x)
+    st = S.ServeState(pop, 0b101101, 10, 0.08)
+    job = S.Job.alloc(pop, 0b101101, 10, 0.08)
+    S.snaps_outlier_scores([job], S.tuning(split=1))
+    torch.cuda.synchronize()
+    po = st.population_outputs()
+    for key in ("eps_count", "indeg", "knn_mean"):
+        assert torch.equal(po[key], getattr(job, key)), key
+    np.testing.assert_allclose(po["eps_mean"].cpu().numpy(), job.eps_mean.cpu().numpy(), rtol=1e-6)
+
+
+def test_mix_vs_alone(S):
+    """Every alert's scores are identical whether its request is scored alone
+    or inside a call that mixes requests of different sizes, populations and
+    subspaces."""
+    rng = np.random.default_rng(11)
+    pops = [S.Population.from_rows(rng.random((n, 15)).astype(np.float32)) for n in (6000, 9000)]
+    states = [S.ServeState(pops[0], 0b111, 10, 0.05), S.ServeState(pops[0], 0b1100001, 10, 0.05),
+              S.ServeState(pops[1], 0b11000000011, 10, 0.12), S.ServeState(pops[1], 0b101, 10, 0.03)]
+    reqs = []
+    for i in range(12):
+        st = states[i % len(states)]
+        m = int(rng.integers(1, 700))
+        reqs.append((st, torch.from_numpy(rng.random((m, st.d)).astype(np.float32)).cuda()))
+    alone = []
+    for st, a in reqs:
+        j = S.AlertJob.alloc(st, a)
+        S.snaps_alerts_score([j])
+        alone.append(j)
+    mixed = [S.AlertJob.alloc(st, a) for st, a in reqs]
+    S.snaps_alerts_score(mixed)
+    torch.cuda.synchronize()
+    for x, y in zip(alone, mixed):
+        for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+            assert torch.equal(getattr(x, key), getattr(y, key)), key
