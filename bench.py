@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import hashlib
 import json
 import math
 import os
@@ -36,6 +37,9 @@ METRIC = "object·subspace outlier scores/sec (batched vs plain, 1 GPU) + p50/p9
 UNIT = "object·subspace scores/s"
 PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak, flop/s
 PEAK_HBM = 8.0e12                # MI355X HBM3E, byte/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_join_c1_all_subspaces_hbm_traffic.md")
+JOIN_SOURCES = ["join_kernel.cuh", "join.hip", "join_inst0.hip", "join_inst1.hip", "join_inst2.hip",
+                "join_inst3.hip", "common.cuh", "snaps_internal.h"]
 
 
 def log(*a):
@@ -133,6 +137,47 @@ def serve_bench(S, G, dev, seconds: float, spaces_per_pop: int = 4, n_streams: i
     return res
 
 
+def join_source_hash() -> str:
+    """sha256 over the join kernel's sources, to tie stored counter readings
+    to the kernel they were taken on."""
+    h = hashlib.sha256()
+    for f in JOIN_SOURCES:
+        with open(os.path.join(ROOT, "paper_2405_20176_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per join launch from the stored rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain-copy calibration), or None if
+    there is none or the join sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line[2:].split(": ", 1) for line in fh if line.startswith("- ") and ": " in line)
+    except OSError:
+        return None
+    if kv.get("join_source_sha256", "").strip("` \n") != join_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"].strip("` \n"))
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib: int):
+    """A plain device-to-device copy of known size, run under rocprofv3 --pmc
+    to scale FETCH_SIZE / WRITE_SIZE readings into bytes."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -142,6 +187,21 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+class _Eager:
+    """One batched pass launched by a direct snaps_outlier_scores call (same
+    interface as a captured plan)."""
+
+    def __init__(self, lib, S, c_jobs, n_jobs, tune, ws):
+        self.lib, self.S, self.c_jobs, self.n_jobs, self.tune, self.ws = lib, S, c_jobs, n_jobs, tune, ws
+
+    def launch(self, stream):
+        rc = self.lib.snaps_outlier_scores(self.c_jobs, self.n_jobs, ctypes.byref(self.tune),
+                                           ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                           ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"batched call failed ({rc}): {self.S.last_error()}")
 
 
 def main():
@@ -154,12 +214,19 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-subspace pass")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--spaces", type=int, default=0, help="debug: use only the first N subspaces")
+    ap.add_argument("--eager", action="store_true", help="launch the batched passes directly, without HIP graphs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain MIB-MiB device copy (counter calibration) and exit")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only (each GPU box has one); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
 
     import torch
     from paper_2405_20176_amd import snaps as S
@@ -210,11 +277,14 @@ def main():
     for s0, e0 in chunks:
         need = lib.snaps_outlier_scores_workspace(job_ptr(s0), e0 - s0, ctypes.byref(tunes[S.PASS_JOIN]))
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
-        trio = [S.Plan(None, tunes[p], ws=ws, c_jobs=job_ptr(s0), n_jobs=e0 - s0)
-                for p in (S.PASS_INDEX, S.PASS_JOIN, S.PASS_RANK)]
+        if a.eager:
+            trio = [_Eager(lib, S, job_ptr(s0), e0 - s0, tunes[p], ws) for p in (S.PASS_INDEX, S.PASS_JOIN, S.PASS_RANK)]
+        else:
+            trio = [S.Plan(None, tunes[p], ws=ws, c_jobs=job_ptr(s0), n_jobs=e0 - s0)
+                    for p in (S.PASS_INDEX, S.PASS_JOIN, S.PASS_RANK)]
         plans.append((ws, trio))
     ws_total = sum(w.numel() for w, _ in plans)
-    log(f"{len(chunks)} plan(s) of 3 graphs built in {time.perf_counter() - t_plan:.1f} s, workspace "
+    log(f"{len(chunks)} plan(s) of 3 {'eager passes' if a.eager else 'graphs'} built in {time.perf_counter() - t_plan:.1f} s, workspace "
         f"{ws_total / 2**30:.2f} GiB, outputs {n_sp * n * 32 / 2**30:.1f} GiB")
 
     def step(events=None):
@@ -264,10 +334,12 @@ def main():
         "dtype": "f32", "data": "synthetic (seeded SNAPShot1-shaped generator; the catalogue itself is not available)",
         "config": {"workload": "SNAPShot1-shaped full run: N=31,693 objects x 15 features, all 32,752 subspaces "
                                "(d=2..15), k=10, per-subspace eps for mean neighbour count 10, batched form "
-                               "(one job table, passes replayed as HIP graphs)",
+                               "(one job table, " + ("passes launched directly)" if a.eager else
+                                                     "passes replayed as HIP graphs)"),
                    "n_objects": n, "n_subspaces": n_sp, "k": k, "subspaces_per_plan": chunk},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": stored_traffic(),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_join (fused kNN + eps join), all instantiations",
                      "flops_per_pair": "3d", "avg_launch_ms": avg_launch_s * 1000.0, "launches": join_launches},
         "join": {"ms_per_step": join_ms / a.steps, "pairs_evaluated_per_step": pairs / a.steps,

@@ -201,7 +201,7 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
         auto take = [&](int r, float dd, int cid) {
             if (dd <= eps2) {
                 cnt[r] += 1;
-                sum[r] += (double)sqrtf(dd);
+                sum[r] += (double)__builtin_amdgcn_sqrtf(dd);   // hardware sqrt, <= 1 ulp
             }
             if (KC > 0) {
                 if (before(dd, cid, kd[r][KS - 1], kid[r][KS - 1])) topk_insert<KS>(kd[r], kid[r], dd, cid);

@@ -165,7 +165,7 @@ __global__ __launch_bounds__(64) void k_alerts(AlertArgs A) {
                     if (dd[j] <= thr) {
                         if (dd[j] <= eps2) {
                             cnt += 1;
-                            sum += (double)sqrtf(dd[j]);
+                            sum += (double)__builtin_amdgcn_sqrtf(dd[j]);   // hardware sqrt, <= 1 ulp
                         }
                         if (KC > 0) {
                             const int cid = __float_as_int(PV(j, D + 1));
