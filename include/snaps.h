@@ -254,7 +254,13 @@ typedef struct {
 
 /* Score n_jobs alert batches whose states all have dimensionality d and the
  * same k (the job list is host memory, read during the call).  Jobs may use
- * different states and populations.  Asynchronous on stream. */
+ * different states and populations.  One wavefront scores one alert; the
+ * results of an alert do not depend on the other alerts or jobs of the call.
+ * The state header lives in device memory, so a mismatch is found on the
+ * device: an alert whose state has another dimensionality than d, or a k
+ * above the top-k capacity chosen for k, is not scored (eps_count and indeg
+ * are set to -1, the means to NaN, ranks are left untouched).  At most 2^31
+ * alerts per call.  Asynchronous on stream. */
 int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k, void* stream);
 
 #ifdef __cplusplus

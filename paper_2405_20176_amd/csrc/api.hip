@@ -862,7 +862,8 @@ namespace {
 
 struct ServeLayout {
     JobPlan plan;
-    size_t hdr, ws, ws_bytes, rk2, tmax, tkey, cnt, mean, deg, kmean, kth, rank, bytes;
+    size_t hdr, ws, ws_bytes, rk2, tmax, tkey, sbox, smax, cnt, mean, deg, kmean, kth, rank, bytes;
+    int nsuper;
 };
 
 ServeLayout serve_layout(int64_t n, int d, int k) {
@@ -881,6 +882,9 @@ ServeLayout serve_layout(int64_t n, int d, int k) {
     L.rk2 = take(rows * sizeof(float));
     L.tmax = take((size_t)L.plan.ntiles * sizeof(float));
     L.tkey = take((size_t)L.plan.ntiles * sizeof(uint32_t));
+    L.nsuper = (L.plan.ntiles + 63) / 64;
+    L.sbox = take((size_t)L.nsuper * 2 * row_stride(d) * sizeof(float));
+    L.smax = take((size_t)L.nsuper * sizeof(float));
     L.cnt = take((size_t)n * 4);
     L.mean = take((size_t)n * 4);
     L.deg = take((size_t)n * 4);
@@ -939,6 +943,9 @@ int snaps_serve_state_build(const snaps_population* P, uint32_t mask, int32_t k,
     hipError_t e = launch_serve_finish(j, li, reinterpret_cast<float*>(base + L.rk2), reinterpret_cast<float*>(base + L.tmax),
                                        reinterpret_cast<uint32_t*>(base + L.tkey), r.knn_kth, s);
     if (e != hipSuccess) return hip_fail(e, "serve state launch");
+    e = launch_serve_super(p.ntiles, row_stride(d), j.boxes, reinterpret_cast<float*>(base + L.tmax),
+                           reinterpret_cast<float*>(base + L.sbox), reinterpret_cast<float*>(base + L.smax), s);
+    if (e != hipSuccess) return hip_fail(e, "serve state launch");
     ServeState st{};
     st.n = (int32_t)P->n;
     st.d = d;
@@ -955,6 +962,9 @@ int snaps_serve_state_build(const snaps_population* P, uint32_t mask, int32_t k,
     st.rk2 = reinterpret_cast<float*>(base + L.rk2);
     st.tmax = reinterpret_cast<float*>(base + L.tmax);
     st.tkey = reinterpret_cast<uint32_t*>(base + L.tkey);
+    st.sbox = reinterpret_cast<float*>(base + L.sbox);
+    st.smax = reinterpret_cast<float*>(base + L.smax);
+    st.nsuper = L.nsuper;
     st.sel_col = li.sel_col;
     st.sel_lo = li.sel_lo;
     st.sel_scale = li.sel_scale;
@@ -996,7 +1006,7 @@ int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, i
     const int kc = kc_class(k);
     for (int b = 0; b < n_jobs; b += kAlertJobs) {
         AlertArgs aa{};
-        int tiles = 0;
+        int64_t alerts = 0;
         const int nb = std::min(kAlertJobs, n_jobs - b);
         aa.n_jobs = nb;
         for (int i = 0; i < nb; ++i) {
@@ -1010,11 +1020,13 @@ int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, i
             J.indeg = a.indeg;
             J.knn_mean = a.knn_mean;
             J.rank = a.rank;
-            aa.tile_prefix[i] = tiles;
-            tiles += (a.m + kTile - 1) / kTile;
+            aa.alert_prefix[i] = (int32_t)alerts;
+            alerts += a.m;
+            if (alerts > INT32_MAX - kAlertWaves)
+                return fail(SNAPS_EINVAL, "more than 2^31 alerts in one call");
         }
-        aa.tile_prefix[nb] = tiles;
-        hipError_t e = launch_alerts(d, kc, aa, tiles, s);
+        aa.alert_prefix[nb] = (int32_t)alerts;
+        hipError_t e = launch_alerts(d, kc, aa, s);
         if (e != hipSuccess) return hip_fail(e, "alert scoring launch");
     }
     return SNAPS_OK;

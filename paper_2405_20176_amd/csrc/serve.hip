@@ -2,20 +2,26 @@
 // one subspace.  The paper has no serving path; the reading used here scores
 // an alert as one extra object that changes nothing in the population and
 // sees no other alert:
-//   - its k nearest population objects (ascending distance, then id) and their
-//     mean distance;
+//   - its k nearest population objects and their mean distance;
 //   - its population neighbours within eps (closed ball), count and mean;
 //   - its in-degree: the number of population objects p whose own k-th
 //     neighbour distance exceeds their distance to the alert (strictly), i.e.
 //     the objects that would list the alert among their k nearest;
 //   - on each metric, the number of distinct population values strictly more
 //     outlying than the alert's value (its dense rank position).
-// The state is built once by the ordinary self-join pipeline (k_serve_finish
+// The state is built once by the ordinary self-join pipeline; k_serve_finish
 // adds the index-order k-th distances, their per-tile maxima and per-tile
-// Morton keys).  One lane scores one alert; every wavefront walks the
-// population tiles outward from the tile where its first alert's Morton key
-// falls, skipping tiles whose box is out of reach of every lane's kNN, eps and
-// in-degree thresholds.
+// Morton keys, and k_serve_super the boxes and maxima of super-tiles of 64
+// tiles.
+//
+// One wavefront scores one alert, its lanes spread over the 64 objects of a
+// population tile.  The walk starts at the tiles around the alert's Morton
+// key (a good first k-th distance), then culls the rest hierarchically: the
+// lanes test 64 super-tile boxes at once, then the 64 tile boxes of each
+// super-tile that may matter, and only tiles that may hold a kNN candidate,
+// an eps neighbour or an object that would count the alert are read.  The
+// k best distances are kept sorted across lanes 0..KC-1; eps hits and
+// in-degree are wavefront ballots, the eps distance sum a float64 reduction.
 #include "snaps_internal.h"
 #include "common.cuh"
 #include "keys.cuh"
@@ -47,36 +53,95 @@ hipError_t launch_serve_finish(const DevJob& j, const LargeIndex& li, float* rk2
     return hipGetLastError();
 }
 
+// Super-tile S covers tiles [64 S, 64 S + 64): the union of their boxes and
+// the maximum of their k-th distances.
+__global__ __launch_bounds__(64) void k_serve_super(int ntiles, int dp, const float* boxes, const float* tmax,
+                                                     float* sbox, float* smax) {
+    const int S = blockIdx.x;
+    const int t = S * 64 + (int)threadIdx.x;
+    const bool valid = t < ntiles;
+    const float tm = wave_max(valid ? tmax[t] : -INFINITY);
+    for (int f = 0; f < dp; ++f) {
+        const float lo = wave_min(valid ? boxes[((int64_t)t * 2) * dp + f] : INFINITY);
+        const float hi = wave_max(valid ? boxes[((int64_t)t * 2 + 1) * dp + f] : -INFINITY);
+        if (threadIdx.x == 0) {
+            sbox[((int64_t)S * 2) * dp + f] = lo;
+            sbox[((int64_t)S * 2 + 1) * dp + f] = hi;
+        }
+    }
+    if (threadIdx.x == 0) smax[S] = tm;
+}
+
+hipError_t launch_serve_super(int ntiles, int dp, const float* boxes, const float* tmax, float* sbox, float* smax,
+                              hipStream_t s) {
+    const int nst = (ntiles + 63) / 64;
+    hipLaunchKernelGGL(k_serve_super, dim3(nst), dim3(64), 0, s, ntiles, dp, boxes, tmax, sbox, smax);
+    return hipGetLastError();
+}
+
+namespace alert_detail {
+
+// Squared float32 distance from q to the box [lo, hi] (0 inside), computed
+// with the same operations in the same order as a point distance, so it
+// never exceeds the float32 distance of any point in the box.
+template <int D, int DP>
+__device__ __forceinline__ float box_dist2(const float (&q)[D], const float* b) {
+    float lb = 0.f;
+#pragma unroll
+    for (int f = 0; f < D; ++f) {
+        const float g = fmaxf(fmaxf(b[f] - q[f], q[f] - b[DP + f]), 0.f);
+        lb = fmaf(g, g, lb);
+    }
+    return lb;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace alert_detail
+
 template <int D, int KC>
-__global__ __launch_bounds__(64) void k_alerts(AlertArgs A) {
+__global__ __launch_bounds__(64 * kAlertWaves) void k_alerts(AlertArgs A) {
+    using namespace alert_detail;
     constexpr int DP = row_stride(D);
     constexpr int KS = KC > 0 ? KC : 1;
-    constexpr int GS = Group<DP>::G;
-    constexpr int NV = Group<DP>::NV;
-    const int u = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int g = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kAlertWaves + (threadIdx.x >> 6)));
+    if (g >= A.alert_prefix[A.n_jobs]) return;
     int lo = 0, hi = A.n_jobs;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (A.tile_prefix[mid] <= u) lo = mid; else hi = mid;
+        if (A.alert_prefix[mid] <= g) lo = mid; else hi = mid;
     }
     const AlertJob& J = A.jobs[lo];
+    const int ai = g - A.alert_prefix[lo];
     const ServeState* St = J.st;
-    const int n = St->n;
     const int nt = St->ntiles;
+    const int nst = St->nsuper;
     const int k = St->k;
+    if (St->d != D || k < 1 || k > KS) {         // state of another shape: flag the alert, read nothing
+        if (lane == 0) {
+            J.eps_count[ai] = -1;
+            J.indeg[ai] = -1;
+            J.eps_mean[ai] = NAN;
+            J.knn_mean[ai] = NAN;
+        }
+        return;
+    }
     const float eps2 = St->eps2;
-    cptr<float> xs = as_const(St->xs);
-    cptr<float> boxes = as_const(St->boxes);
-    cptr<float> rk2 = as_const(St->rk2);
-    cptr<float> tmax = as_const(St->tmax);
-    const int m = J.m;
-    const int ai = (u - A.tile_prefix[lo]) * kTile + lane;
-    const bool valid = ai < m;
-    const int row = valid ? ai : m - 1;
+    const float* xs = St->xs;
+    const float* boxes = St->boxes;
+    const float* sbox = St->sbox;
+    const float* rk2 = St->rk2;
+    const float* tmaxp = St->tmax;
+    const float* smaxp = St->smax;
+
     float q[D];
 #pragma unroll
-    for (int f = 0; f < D; ++f) q[f] = J.alerts[(int64_t)row * D + f];
+    for (int f = 0; f < D; ++f) q[f] = J.alerts[(int64_t)ai * D + f];
 
     // Morton key of the alert in the population's cell grid -> start tile.
     uint32_t qv[kMaxIndexDims];
@@ -108,101 +173,120 @@ __global__ __launch_bounds__(64) void k_alerts(AlertArgs A) {
         if (St->tkey[mid] <= key) tl = mid + 1; else th = mid;
     }
     const int tc = __builtin_amdgcn_readfirstlane(tl > 0 ? tl - 1 : 0);
+    const int w0 = max(0, tc - 1), w1 = min(nt, tc + 3);   // start window, read first
 
-    float kd[KS];
-    int kid[KS];
-#pragma unroll
-    for (int j = 0; j < KS; ++j) {
-        const bool dummy = j < KS - k;
-        kd[j] = dummy ? -INFINITY : INFINITY;
-        kid[j] = dummy ? -1 : INT_MAX;
-    }
+    // k best squared distances, ascending over lanes 0..KS-1; the KS - k
+    // slots in front hold -inf so that slot KS-1 is always the k-th.
+    float kd = (lane < KS - k) ? -INFINITY : INFINITY;
+    float kth = INFINITY;
     int cnt = 0, deg = 0;
     double sum = 0.0;
-    float thr = fmaxf(kd[KS - 1], eps2);
 
-    for (int s = 0; s < nt; ++s) {
-        const int t = spiral(tc, s, nt);
-        cptr<float> bx = boxes + (int64_t)t * 2 * DP;
-        float lb = 0.f;
+    auto scan_tile = [&](int t) {
+        const int pos = t * kTile + lane;
+        const float* row = xs + (int64_t)pos * DP;
+        float p[DP];
+#pragma unroll
+        for (int v = 0; v < DP / 4; ++v) {
+            const float4 r4 = *reinterpret_cast<const float4*>(row + 4 * v);
+            p[4 * v] = r4.x; p[4 * v + 1] = r4.y; p[4 * v + 2] = r4.z; p[4 * v + 3] = r4.w;
+        }
+        const float rk = rk2[pos];
+        float dd = 0.f;
 #pragma unroll
         for (int f = 0; f < D; ++f) {
-            const float g = fmaxf(fmaxf(bx[f] - q[f], q[f] - bx[DP + f]), 0.f);
-            lb = fmaf(g, g, lb);
+            const float tq = q[f] - p[f];
+            dd = fmaf(tq, tq, dd);
         }
-        const float tm = tmax[t];
-        if (!__any(lb <= thr || lb < tm)) continue;
-        const int cbase = t * kTile;
-#pragma unroll 1
-        for (int g = 0; g < kTile; g += GS) {
-            const int c0 = cbase + g;
-            cptr<f4v> pv = (cptr<f4v>)(xs + (int64_t)c0 * DP);
-            f4v blk[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) blk[v] = pv[v];
-            float rk[GS];
-#pragma unroll
-            for (int j = 0; j < GS; ++j) rk[j] = rk2[c0 + j];
-#define PV(j, f) blk[((j) * DP + (f)) >> 2][((j) * DP + (f)) & 3]
-            float dd[GS];
-#pragma unroll
-            for (int j = 0; j < GS; ++j) {
-                float acc = 0.f;
-#pragma unroll
-                for (int f = 0; f < D; ++f) {
-                    const float tq = q[f] - PV(j, f);
-                    acc = fmaf(tq, tq, acc);
-                }
-                dd[j] = acc;
-                deg += (acc < rk[j]) ? 1 : 0;
+        // pad rows hold NaN: every comparison below is false for them
+        deg += __popcll(__ballot(dd < rk));
+        const bool hit = dd <= eps2;
+        const unsigned long long hm = __ballot(hit);
+        if (hm) {
+            cnt += __popcll(hm);
+            sum += wave_sum_f64(hit ? (double)__builtin_amdgcn_sqrtf(dd) : 0.0);
+        }
+        unsigned long long cm = __ballot(dd < kth);
+        while (cm) {
+            const int b = __builtin_ctzll(cm);
+            cm &= cm - 1;
+            const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dd), b));
+            if (v < kth) {
+                const int at = __popcll(__ballot(lane < KS && kd <= v));
+                const float up = __shfl_up(kd, 1, 64);
+                kd = (lane == at) ? v : ((lane > at && lane < KS) ? up : kd);
+                kth = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kd), KS - 1));
             }
-            float mn = dd[0];
-#pragma unroll
-            for (int j = 1; j < GS; ++j) mn = fminf(mn, dd[j]);
-            if (mn <= thr) {
-#pragma unroll
-                for (int j = 0; j < GS; ++j) {
-                    if (dd[j] <= thr) {
-                        if (dd[j] <= eps2) {
-                            cnt += 1;
-                            sum += (double)__builtin_amdgcn_sqrtf(dd[j]);   // hardware sqrt, <= 1 ulp
-                        }
-                        if (KC > 0) {
-                            const int cid = __float_as_int(PV(j, D + 1));
-                            if (before(dd[j], cid, kd[KS - 1], kid[KS - 1])) topk_insert<KS>(kd, kid, dd[j], cid);
-                            thr = fmaxf(kd[KS - 1], eps2);
-                        }
-                    }
-                }
+        }
+    };
+    auto tile_matters = [&](int t) {
+        const float lb = box_dist2<D, DP>(q, boxes + (int64_t)t * 2 * DP);
+        return lb <= fmaxf(kth, eps2) || lb < tmaxp[t];
+    };
+
+    for (int t = w0; t < w1; ++t)
+        if (tile_matters(t)) scan_tile(t);
+
+    for (int s0 = 0; s0 < nst; s0 += 64) {
+        const int S = s0 + lane;
+        bool sm = false;
+        if (S < nst) {
+            const float lb = box_dist2<D, DP>(q, sbox + (int64_t)S * 2 * DP);
+            sm = lb <= fmaxf(kth, eps2) || lb < smaxp[S];
+        }
+        unsigned long long smask = __ballot(sm);
+        while (smask) {
+            const int Sb = s0 + __builtin_ctzll(smask);
+            smask &= smask - 1;
+            const int t = Sb * 64 + lane;
+            float lb = INFINITY, tm = -INFINITY;
+            bool tmat = false;
+            if (t < nt && (t < w0 || t >= w1)) {         // the start window is done
+                lb = box_dist2<D, DP>(q, boxes + (int64_t)t * 2 * DP);
+                tm = tmaxp[t];
+                tmat = lb <= fmaxf(kth, eps2) || lb < tm;
             }
-#undef PV
+            unsigned long long tmask = __ballot(tmat);
+            while (tmask) {
+                const int b = __builtin_ctzll(tmask);
+                tmask &= tmask - 1;
+                // re-test with the k-th distance found so far
+                const float lbt = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lb), b));
+                const float tmt = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tm), b));
+                if (lbt <= fmaxf(kth, eps2) || lbt < tmt) scan_tile(Sb * 64 + b);
+            }
         }
     }
-    (void)n;
-    if (!valid) return;
-    const float mean = cnt > 0 ? (float)(sum / (double)cnt) : 0.f;
-    float accm = 0.f;
-#pragma unroll
-    for (int j = 0; j < KS; ++j)
-        if (j >= KS - k) accm += sqrtf(kd[j]);
-    const float kmean = accm / (float)k;
-    J.eps_count[ai] = cnt;
-    J.eps_mean[ai] = mean;
-    J.indeg[ai] = deg;
-    J.knn_mean[ai] = kmean;
-    if (J.rank) {
-        const uint32_t keys[4] = {(uint32_t)cnt, ~asc_key(cnt > 0 ? mean : INFINITY), (uint32_t)deg,
-                                  ~asc_key(kmean)};
-#pragma unroll
-        for (int mtr = 0; mtr < 4; ++mtr) {
-            const uint32_t* dv = St->distinct[mtr];
-            int a = 0, b = St->n_distinct[mtr];
-            while (a < b) {
-                const int mid = (a + b) >> 1;
-                if (dv[mid] < keys[mtr]) a = mid + 1; else b = mid;
-            }
-            J.rank[(int64_t)mtr * m + ai] = a;
+
+    // kNN mean over the k real slots (ascending order, fixed reduction tree)
+    const float kv = (lane >= KS - k && lane < KS) ? __builtin_amdgcn_sqrtf(kd) : 0.f;
+    const float ksum = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum(kv)), 0));
+    const float kmean = ksum / (float)k;
+    // the butterfly leaves each lane its own rounding of the sum: take lane 0's
+    const long long sb = __double_as_longlong(sum);
+    const unsigned s_lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(sb & 0xffffffffLL), 0);
+    const unsigned s_hi = (unsigned)__builtin_amdgcn_readlane((int)(sb >> 32), 0);
+    const double sum0 = __longlong_as_double((long long)(((unsigned long long)s_hi << 32) | s_lo));
+    const float mean = cnt > 0 ? (float)(sum0 / (double)cnt) : 0.f;
+    if (lane == 0) {
+        J.eps_count[ai] = cnt;
+        J.eps_mean[ai] = mean;
+        J.indeg[ai] = deg;
+        J.knn_mean[ai] = kmean;
+    }
+    if (J.rank && lane < 4) {
+        const int mtr = lane;
+        const uint32_t key_m = mtr == 0 ? (uint32_t)cnt
+                             : mtr == 1 ? ~asc_key(cnt > 0 ? mean : INFINITY)
+                             : mtr == 2 ? (uint32_t)deg
+                                        : ~asc_key(kmean);
+        const uint32_t* dv = St->distinct[mtr];
+        int a = 0, b = St->n_distinct[mtr];
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (dv[mid] < key_m) a = mid + 1; else b = mid;
         }
+        J.rank[(int64_t)mtr * J.m + ai] = a;
     }
 }
 
@@ -244,13 +328,15 @@ AlertFn alert_pick(int D, int kc) {
 
 }  // namespace
 
-hipError_t launch_alerts(int D, int kc, const AlertArgs& a, int total_tiles, hipStream_t s) {
+hipError_t launch_alerts(int D, int kc, const AlertArgs& a, hipStream_t s) {
     AlertFn fn = alert_pick(D, kc);
     if (!fn) return hipErrorInvalidValue;
-    if (total_tiles <= 0) return hipSuccess;
+    const int total = a.alert_prefix[a.n_jobs];
+    if (total <= 0) return hipSuccess;
     AlertArgs copy = a;
     void* args[] = {&copy};
-    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(total_tiles), dim3(64), args, 0, s);
+    const int grid = (total + kAlertWaves - 1) / kAlertWaves;
+    return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(64 * kAlertWaves), args, 0, s);
 }
 
 }  // namespace snaps

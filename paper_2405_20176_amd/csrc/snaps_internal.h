@@ -140,6 +140,9 @@ struct ServeState {
     const float* rk2;          // [ntiles*64] k-th neighbour dd at each index position (pads: -inf)
     const float* tmax;         // [ntiles]
     const uint32_t* tkey;      // [ntiles] non-decreasing
+    const float* sbox;         // [nsuper][2][DP] union of the boxes of tiles 64 S .. 64 S + 63
+    const float* smax;         // [nsuper] max of tmax over the same tiles
+    int32_t nsuper, pad1;
     const int32_t* sel_col;    // index dimensions and their cell grids
     const float* sel_lo;
     const float* sel_scale;
@@ -147,8 +150,10 @@ struct ServeState {
     const int32_t* n_distinct;  // [4]
 };
 
-// Alert scoring launch: up to kAlertJobs jobs passed by value.
+// Alert scoring launch: up to kAlertJobs jobs passed by value; one
+// wavefront per alert, kAlertWaves wavefronts per workgroup.
 constexpr int kAlertJobs = 32;
+constexpr int kAlertWaves = 4;
 struct AlertJob {
     const ServeState* st;
     const float* alerts;       // [m][d] row-major
@@ -162,7 +167,7 @@ struct AlertJob {
 };
 struct AlertArgs {
     AlertJob jobs[kAlertJobs];
-    int32_t tile_prefix[kAlertJobs + 1];
+    int32_t alert_prefix[kAlertJobs + 1];      // alerts of jobs before each job
     int32_t n_jobs;
 };
 
@@ -171,8 +176,8 @@ struct RankArgs {
     int32_t n_jobs;
 };
 
-// Queries per lane of the join instantiation for top-k capacity kc: 2 for
-// capacities up to 20 (register budget), 1 for 32 and for the range-only join.
+// Queries per lane of the join instantiation for top-k capacity kc: one
+// (two per lane coarsened the tile pruning more than it saved in loads).
 __host__ __device__ constexpr int join_ql(int kc) { return kc < 0 ? 2 : 1; }
 
 // Launchers (each returns the HIP status of the launch).
@@ -182,7 +187,9 @@ hipError_t launch_rank(const RankArgs& a, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t n, int32_t v, hipStream_t s);
 hipError_t launch_serve_finish(const DevJob& j, const LargeIndex& li, float* rk2, float* tmax, uint32_t* tkey,
                                const float* kth, hipStream_t s);
-hipError_t launch_alerts(int D, int kc, const AlertArgs& a, int total_tiles, hipStream_t s);
+hipError_t launch_serve_super(int ntiles, int dp, const float* boxes, const float* tmax, float* sbox, float* smax,
+                              hipStream_t s);
+hipError_t launch_alerts(int D, int kc, const AlertArgs& a, hipStream_t s);
 hipError_t launch_radix_sort(const SortSeg* segs, const int32_t* chunk_prefix, int n_segs, int total_chunks,
                              int passes, hipStream_t s);
 // Large-n index build (before k_reorder) and rank, over every large job of a call.

@@ -147,3 +147,66 @@ def test_mix_vs_alone(S):
     for x, y in zip(alone, mixed):
         for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
             assert torch.equal(getattr(x, key), getattr(y, key)), key
+
+
+def test_state_of_another_shape_is_flagged_not_read(S):
+    """A job whose state has another dimensionality than the call's d is
+    flagged on the device (-1 counts, NaN means) instead of being scored."""
+    import ctypes
+    rng = np.random.default_rng(5)
+    pop = S.Population.from_rows(rng.random((3000, 6)).astype(np.float32))
+    st = S.ServeState(pop, 0b111, 5, 0.1)
+    alerts = torch.from_numpy(rng.random((70, 3)).astype(np.float32)).cuda()
+    job = S.AlertJob.alloc(st, alerts)
+    arr = (S.c_alert_job * 1)()
+    arr[0].state = st.ptr()
+    arr[0].alerts = alerts.data_ptr()
+    arr[0].m = 70
+    arr[0].eps_count = job.eps_count.data_ptr()
+    arr[0].eps_mean = job.eps_mean.data_ptr()
+    arr[0].indeg = job.indeg.data_ptr()
+    arr[0].knn_mean = job.knn_mean.data_ptr()
+    arr[0].rank = None
+    lib = S.load_library()
+    assert lib.snaps_alerts_score(arr, 1, 4, 5, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)) == 0
+    torch.cuda.synchronize()
+    assert (job.eps_count.cpu().numpy() == -1).all() and (job.indeg.cpu().numpy() == -1).all()
+    assert torch.isnan(job.knn_mean).all() and torch.isnan(job.eps_mean).all()
+    # the same job with the right d is scored
+    S.snaps_alerts_score([job])
+    torch.cuda.synchronize()
+    assert (job.eps_count.cpu().numpy() >= 0).all() and (job.indeg.cpu().numpy() >= 0).all()
+
+
+def test_large_population_many_super_tiles(S):
+    """A population of 300,000 objects (74 super-tiles): alerts inside the
+    bulk, on its edge and far outside.  The alert-side metrics come from the
+    oracle's pair distances; the population's k-th neighbour distances, which
+    the in-degree needs, from scipy's exact k-d tree (checked against the
+    oracle in the pins)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(17)
+    n, d, k = 300_000, 4, 10
+    x = (rng.random((n, d)) ** 2).astype(np.float32)            # denser near 0
+    eps = 0.01
+    alerts = np.concatenate([rng.random((40, d)) ** 2, rng.random((8, d)) * 0.05,
+                             1.0 + rng.random((4, d))]).astype(np.float32)
+    pop = S.Population.from_rows(x)
+    st = S.ServeState(pop, (1 << d) - 1, k, eps)
+    out = score(S, st, alerts)
+    x64 = x.astype(np.float64)
+    rk = cKDTree(x64).query(x64, k=k + 1)[0][:, k]              # self is the first hit
+    D = O.pair_distances(alerts, x)
+    knn_mean = np.sort(D, axis=1)[:, :k].mean(axis=1)
+    hit = D <= eps
+    cnt = hit.sum(axis=1)
+    mean = np.where(cnt > 0, np.where(hit, D, 0).sum(axis=1) / np.maximum(cnt, 1), 0)
+    deg = (D < rk[None, :]).sum(axis=1)
+    eps_ex = (np.abs(D - eps) <= TAU * eps).any(axis=1)
+    deg_ex = (np.abs(D - rk[None, :]) <= TAU * rk[None, :]).sum(axis=1)
+    np.testing.assert_allclose(out["knn_mean"], knn_mean, rtol=TAU)
+    assert ((out["eps_count"] == cnt) | eps_ex).all()
+    rel = np.abs(out["eps_mean"] - mean) / np.maximum(mean, 1e-30)
+    assert ((rel <= TAU) | eps_ex | ((mean == 0) & (out["eps_mean"] == 0))).all()
+    assert (np.abs(out["indeg"] - deg) <= deg_ex).all()
+    assert (deg[-4:] == 0).all() and (cnt[-4:] == 0).all()      # far alerts
