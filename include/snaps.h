@@ -108,7 +108,11 @@ typedef struct {
     int32_t split;          /* 0 auto, else waves sharing one query tile: 1, 2, 4 or 8 */
     int32_t index_dims;     /* 0 auto (min(d, 6), as Sec. 3.8.1), else 1..min(d, 6) */
     int32_t filter;         /* 0 auto, 1 direct distance form only,
-                               2 expanded-form prefilter with exact direct recheck */
+                               2 expanded-form prefilter on the vector ALU with exact direct
+                               recheck, 3 the same prefilter as a dense contraction on the
+                               matrix cores (MFMA), exact direct recheck; with split or mq
+                               above 1 the vector-ALU prefilter runs instead.  All give
+                               identical results. */
     int32_t passes;         /* 0 = all; else a mask of SNAPS_PASS_*.  A call that runs the join
                                or rank pass without the index pass must follow a call with the
                                same jobs and workspace that ran the earlier passes. */

@@ -84,7 +84,7 @@ int check_tuning(const snaps_tuning* t) {
     if (!(t->split == 0 || t->split == 1 || t->split == 2 || t->split == 4 || t->split == 8))
         return fail(SNAPS_EINVAL, "tuning.split must be 0, 1, 2, 4 or 8");
     if (t->index_dims < 0 || t->index_dims > kMaxIndexDims) return fail(SNAPS_EINVAL, "tuning.index_dims must be in [0, 6]");
-    if (t->filter < 0 || t->filter > 2) return fail(SNAPS_EINVAL, "tuning.filter must be 0, 1 or 2");
+    if (t->filter < 0 || t->filter > 3) return fail(SNAPS_EINVAL, "tuning.filter must be 0, 1, 2 or 3");
     if (t->passes < 0 || t->passes > 7) return fail(SNAPS_EINVAL, "tuning.passes must be a mask of SNAPS_PASS_*");
     if (!(t->mq == 0 || t->mq == 1 || t->mq == 2 || t->mq == 4 || t->mq == 8))
         return fail(SNAPS_EINVAL, "tuning.mq must be 0, 1, 2, 4 or 8");
@@ -302,7 +302,7 @@ int launch_joins(const Meta& meta, const std::vector<ClassPlan>& plans, const Tu
                  hipStream_t s) {
     int64_t all_units = 0;
     for (const auto& p : plans) all_units += p.units;
-    const int xf = tn.filter == 1 ? 0 : 1;
+    const int xf_pref = tn.filter == 1 ? 0 : tn.filter == 3 ? 2 : 1;
     hipError_t fe = launch_fill_i32(meta.counters, meta.n_counters, 0, s);
     if (fe != hipSuccess) return hip_fail(fe, "counter reset");
     for (int c = 0; c < kNumClasses; ++c) {
@@ -312,6 +312,8 @@ int launch_joins(const Meta& meta, const std::vector<ClassPlan>& plans, const Tu
         static const int kKc[5] = {0, 5, 10, 20, 32};
         const int kc = kKc[c % 5];
         const int split = mq > 1 ? 1 : choose_split(tn, all_units, cus, kc);
+        // the matrix-core kernel runs one wavefront per query tile
+        const int xf = (xf_pref == 2 && (split > 1 || mq > 1)) ? 1 : xf_pref;
         JoinArgs a{};
         a.table = meta.table;
         a.order = meta.order;

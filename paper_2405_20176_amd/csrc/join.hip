@@ -1,6 +1,7 @@
 // Dispatch of the fused join kernel over its instantiations (dimensionality,
 // top-k capacity, prefilter flavour), occupancy query and launch.
 #include "join_kernel.cuh"
+#include "join_mfma.cuh"
 
 namespace snaps {
 
@@ -13,7 +14,7 @@ int kc_class(int k) {
 }
 
 size_t join_lds_bytes(int kc, int split) {
-    if (split <= 1) return 0;
+    if (split <= 1) return 0;   // also the matrix-core kernel (always one wavefront)
     const int ks = kc > 0 ? kc : 1;
     // per wavefront and query slot: top-k distances and ids, eps counts, then
     // the float64 eps sums (the offset of the last block is a multiple of 256)
@@ -22,7 +23,13 @@ size_t join_lds_bytes(int kc, int split) {
 
 namespace {
 
+// xf: 0 direct form, 1 vector-ALU prefilter, 2 matrix-core prefilter.
 JoinFn pick(int D, int kc, int xf) {
+    if (xf == 2) {
+        if (D >= 2 && D <= 8) return join_mfma_pick_group0(D, kc);
+        if (D >= 9 && D <= 16) return join_mfma_pick_group1(D, kc);
+        return nullptr;
+    }
     if (D >= 2 && D <= 6) return join_pick_group0(D, kc, xf);
     if (D >= 7 && D <= 10) return join_pick_group1(D, kc, xf);
     if (D >= 11 && D <= 13) return join_pick_group2(D, kc, xf);

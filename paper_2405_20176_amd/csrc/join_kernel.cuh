@@ -104,6 +104,40 @@ struct Group {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+// Next work unit of a persistent join workgroup: thread 0 takes one from the
+// workgroup's home queue (its XCD), or steals from the others once it is
+// drained; every thread gets the unit u, its queue qu and the queue-local
+// index lo of its job (prefix[lo] <= u < prefix[lo + 1]).  False when every
+// queue is drained.  Contains two workgroup barriers.
+__device__ __forceinline__ bool next_unit(const JoinArgs& A, int home, unsigned& drained, int& s_unit, int& s_queue,
+                                          int& u, int& qu, int& lo) {
+    if (threadIdx.x == 0) {
+        int got = -1, gq = 0;
+        for (int i = 0; i < kQueues && got < 0; ++i) {
+            const int qq = (home + i) % kQueues;
+            if ((drained >> qq) & 1u) continue;
+            const int v = A.q_units[qq] > 0 ? atomicAdd(A.counter + qq, 1) : A.q_units[qq];
+            if (v < A.q_units[qq]) { got = v; gq = qq; }
+            else drained |= 1u << qq;
+        }
+        s_unit = got;
+        s_queue = gq;
+    }
+    __syncthreads();
+    u = __builtin_amdgcn_readfirstlane(s_unit);
+    qu = __builtin_amdgcn_readfirstlane(s_queue);
+    __syncthreads();
+    if (u < 0) return false;
+    const int32_t* prefix = A.unit_prefix + A.q_prefix_off[qu];
+    int l = 0, h = A.q_jobs[qu];
+    while (h - l > 1) {
+        const int mid = (l + h) >> 1;
+        if (prefix[mid] <= u) l = mid; else h = mid;
+    }
+    lo = l;
+    return true;
+}
+
 }  // namespace join_detail
 
 using namespace join_detail;
@@ -126,31 +160,9 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
     const int home = blockIdx.x % kQueues;                   // this workgroup's XCD
     unsigned drained = 0;                                     // queues found empty (thread 0)
     for (;;) {
-        if (threadIdx.x == 0) {
-            int got = -1, gq = 0;
-            for (int i = 0; i < kQueues && got < 0; ++i) {
-                const int qq = (home + i) % kQueues;
-                if ((drained >> qq) & 1u) continue;
-                const int v = A.q_units[qq] > 0 ? atomicAdd(A.counter + qq, 1) : A.q_units[qq];
-                if (v < A.q_units[qq]) { got = v; gq = qq; }
-                else drained |= 1u << qq;
-            }
-            s_unit = got;
-            s_queue = gq;
-        }
-        __syncthreads();
-        const int u = __builtin_amdgcn_readfirstlane(s_unit);
-        const int qu = __builtin_amdgcn_readfirstlane(s_queue);
-        __syncthreads();
-        if (u < 0) break;
-
-        // Locate the job of unit u in queue qu: prefix[j] <= u < prefix[j+1].
+        int u, qu, lo;
+        if (!next_unit(A, home, drained, s_unit, s_queue, u, qu, lo)) break;
         const int32_t* prefix = A.unit_prefix + A.q_prefix_off[qu];
-        int lo = 0, hi = A.q_jobs[qu];
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (prefix[mid] <= u) lo = mid; else hi = mid;
-        }
         const int tu = (u - prefix[lo]) * QL * W;            // first query tile of the unit
         const int t0 = W > 1 ? tu + wave * QL : tu;          // this wavefront's first query tile
         const DevJob* Jp = A.table + A.order[A.q_order_off[qu] + lo];

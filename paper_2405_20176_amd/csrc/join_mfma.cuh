@@ -1,0 +1,303 @@
+// Fused kNN + eps self-join with the expanded-form prefilter on the matrix
+// cores.  Same work units, walk, pruning, per-query state and outputs as
+// k_join with one wavefront per workgroup and one query per lane; what
+// changes is how a (query tile, candidate tile) pair is screened.
+//
+// The prefilter test of query i and candidate j is h_j + q_i . p_j >= lim_i
+// (h_j = -pn_j (1 - c0) / 2 stored in the candidate's row, lim_i from
+// xf_limit).  For a 64 x 64 tile pair the scores h_j + q_i . p_j - lim_i are
+// a dense contraction, computed by v_mfma_f32_32x32x2f32 in four 32 x 32
+// blocks over ceil(d / 2) + 1 K-steps: the coordinates, then one step whose
+// two K slots carry (-lim_i, 1) and (1, h_j).  A pair passes when its
+// accumulator is >= 0.  The rounding of that accumulation, with |lim_i|
+// among the summed magnitudes, stays inside the prefilter's margin (the
+// margin also allows products and sums that round separately), so every
+// candidate the exact direct form would accept still passes.
+//
+// Operand layouts (32 x 32 x 2, one block): lane l holds A[l % 32][l / 32]
+// and B[l / 32][l % 32]; accumulator register r of lane l is element
+// (8 (r / 4) + 4 (l / 32) + r % 4, l % 32).  Rows are queries, columns
+// candidates.  Most tile pairs have no passing pair, which a per-lane
+// maximum over the accumulators and one ballot establish.  Otherwise the
+// ballot of each accumulator register gives, in its low and high 32 bits,
+// the passing candidates of two queries in one candidate block; those bits
+// are written into the owning lanes' per-query candidate masks, whose union
+// is then walked candidate by candidate in ascending order (a
+// wavefront-uniform loop; the candidate row arrives by scalar loads).  Every
+// lane whose mask holds the candidate re-evaluates the exact direct-form
+// distance and updates its query's kNN list and eps sums exactly as k_join
+// does, in the same order, so the results are identical to both k_join
+// flavours.
+#pragma once
+
+#include "join_kernel.cuh"
+
+namespace snaps {
+
+namespace mfma_detail {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+// Row (within the 64-query tile) of accumulator register r of block row rb
+// in lane half h.
+__device__ __forceinline__ constexpr int acc_row(int rb, int r, int h) {
+    return 32 * rb + 8 * (r >> 2) + 4 * h + (r & 3);
+}
+
+
+}  // namespace mfma_detail
+
+template <int D, int KC>
+__global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
+    using namespace mfma_detail;
+    constexpr int DP = row_stride(D);
+    constexpr int KS = KC > 0 ? KC : 1;
+    constexpr int KSTEPS = (D + 1) / 2;      // coordinate steps; one more carries -lim and h
+    constexpr float cq = (float)(2 * (8 * D + 24)) * 5.9604644775390625e-8f;
+    __shared__ int s_unit, s_queue;
+
+    const int lane = threadIdx.x;
+    const int half = lane >> 5;
+    const int col = lane & 31;
+    const int home = blockIdx.x % kQueues;
+    unsigned drained = 0;
+    for (;;) {
+        int u, qu, lo;
+        if (!next_unit(A, home, drained, s_unit, s_queue, u, qu, lo)) break;
+        const int32_t* prefix = A.unit_prefix + A.q_prefix_off[qu];
+        const int t0 = u - prefix[lo];
+        const DevJob* Jp = A.table + A.order[A.q_order_off[qu] + lo];
+        const int n = Jp->n;
+        const int nt = Jp->ntiles;
+        const int k = KC > 0 ? Jp->k : 0;
+        const float eps2 = Jp->eps2;
+        const int prune = Jp->prune;
+        const float* xs_g = Jp->xs;
+        cptr<float> xs = as_const(xs_g);
+        cptr<float> boxes = as_const((const float*)Jp->boxes);
+
+        // Per-lane query (lane = query row of the tile), as in k_join.
+        const int qpos = t0 * kTile + lane;
+        const int qrow = qpos < n ? qpos : (n - 1);
+        float q[D];
+#pragma unroll
+        for (int f = 0; f < D; ++f) q[f] = xs_g[(int64_t)qrow * DP + f];
+        float kd[KS];
+        int kid[KS];
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            const bool dummy = j < KS - k;
+            kd[j] = dummy ? -INFINITY : INFINITY;
+            kid[j] = dummy ? -1 : INT_MAX;
+        }
+        int cnt = 0;
+        double sum = 0.0;
+        float thr = KC > 0 ? fmaxf(kd[KS - 1], eps2) : eps2;
+        float qn = 0.f;
+#pragma unroll
+        for (int f = 0; f < D; ++f) qn = fmaf(q[f], q[f], qn);
+        float lim = xf_limit(qn, thr, cq);
+        const int nq = max(0, min(kTile, n - t0 * kTile));
+        long long pairs = 0;
+        int scanned = 0, skipped = 0;
+
+        // A operands: query rows 32 rb + col of the tile, dimensions 2 s + half
+        // (pad rows beyond n hold NaN and never pass; a pad dimension is 0),
+        // then (-lim, 1) of the same query.
+        float av[2][KSTEPS + 1];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const float* rowp = xs_g + (int64_t)(t0 * kTile + 32 * rb + col) * DP + half;
+#pragma unroll
+            for (int s = 0; s < KSTEPS; ++s) {
+                const float v = rowp[2 * s];
+                av[rb][s] = (D % 2 == 1 && s == KSTEPS - 1 && half) ? 0.f : v;
+            }
+        }
+        auto refresh_limits = [&]() {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const float l = __shfl(lim, 32 * rb + col, 64);
+                av[rb][KSTEPS] = half ? 1.f : -l;
+            }
+        };
+        refresh_limits();
+
+        // Exact re-evaluation of one candidate (same operations as k_join).
+        auto take = [&](float dd, int cid) {
+            if (dd <= eps2) {
+                cnt += 1;
+                sum += (double)__builtin_amdgcn_sqrtf(dd);   // hardware sqrt, <= 1 ulp
+            }
+            if (KC > 0) {
+                if (before(dd, cid, kd[KS - 1], kid[KS - 1])) topk_insert<KS>(kd, kid, dd, cid);
+                const float nthr = fmaxf(kd[KS - 1], eps2);
+                const bool moved = nthr != thr;
+                thr = nthr;
+                lim = xf_limit(qn, thr, cq);
+                return moved;
+            }
+            return false;
+        };
+
+        for (int s = 0; s < nt; ++s) {
+            const int t = spiral(t0, s, nt);
+            if (prune) {
+                cptr<float> bx = boxes + (int64_t)t * 2 * DP;
+                float lb = 0.f;
+#pragma unroll
+                for (int f = 0; f < D; ++f) {
+                    const float g = fmaxf(fmaxf(bx[f] - q[f], q[f] - bx[DP + f]), 0.f);
+                    lb = fmaf(g, g, lb);
+                }
+                if (!__any(lb <= thr)) {
+                    ++skipped;
+                    continue;
+                }
+            }
+            ++scanned;
+            pairs += (long long)nq * min(kTile, n - t * kTile);
+            const int cbase = t * kTile;
+
+            // B operands: candidate rows 32 cb + col of the tile, then (1, h).
+            float bv[2][KSTEPS + 1];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                // lane half 0 reads the even dimensions, half 1 the odd ones
+                const float* rowc = xs_g + (int64_t)(cbase + 32 * cb + col) * DP + half;
+#pragma unroll
+                for (int s2 = 0; s2 < KSTEPS; ++s2) {
+                    const float v = rowc[2 * s2];
+                    bv[cb][s2] = (D % 2 == 1 && s2 == KSTEPS - 1 && half) ? 0.f : v;
+                }
+                const float h = rowc[D - half];
+                bv[cb][KSTEPS] = half ? h : 1.f;
+            }
+            f16v acc[2][2];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    acc[rb][cb] = f16v{};
+#pragma unroll
+                    for (int s2 = 0; s2 <= KSTEPS; ++s2)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][s2], bv[cb][s2], acc[rb][cb], 0, 0, 0);
+                }
+
+            // Screen: does any pair of the tile pass?  (NaN pads never do.)
+            float mx = -INFINITY;
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) mx = fmaxf(mx, acc[rb][cb][r]);
+            if (!__any(mx >= 0.f)) continue;
+
+            // Per-query candidate masks (this lane's query) and their union.
+            unsigned m_lo = 0, m_hi = 0;
+            unsigned u_lo = 0, u_hi = 0;
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const unsigned long long b0 = __ballot(acc[rb][0][r] >= 0.f);
+                    const unsigned long long b1 = __ballot(acc[rb][1][r] >= 0.f);
+                    if (b0 | b1) {
+                        const int i0 = acc_row(rb, r, 0);
+                        if (lane == i0) {
+                            m_lo = (unsigned)b0;
+                            m_hi = (unsigned)b1;
+                        }
+                        if (lane == i0 + 4) {
+                            m_lo = (unsigned)(b0 >> 32);
+                            m_hi = (unsigned)(b1 >> 32);
+                        }
+                        u_lo |= (unsigned)b0 | (unsigned)(b0 >> 32);
+                        u_hi |= (unsigned)b1 | (unsigned)(b1 >> 32);
+                    }
+                }
+            unsigned long long un = ((unsigned long long)u_hi << 32) | u_lo;
+            if (un) {
+                bool moved = false;
+                while (un) {
+                    const int j = __builtin_ctzll(un);
+                    un &= un - 1;
+                    const int c = cbase + j;
+                    cptr<f4v> pv = (cptr<f4v>)(xs + (int64_t)c * DP);
+                    f4v blk[DP / 4];
+#pragma unroll
+                    for (int v = 0; v < DP / 4; ++v) blk[v] = pv[v];
+#define PV(f) blk[(f) >> 2][(f) & 3]
+                    const unsigned bit = j < 32 ? (m_lo >> j) : (m_hi >> (j - 32));
+                    if ((bit & 1u) && c != qpos) {
+                        float dd = 0.f;
+#pragma unroll
+                        for (int f = 0; f < D; ++f) {
+                            const float tq = q[f] - PV(f);
+                            dd = fmaf(tq, tq, dd);
+                        }
+                        if (dd <= thr) moved |= take(dd, __float_as_int(PV(D + 1)));
+                    }
+#undef PV
+                }
+                if (__any(moved)) refresh_limits();
+            }
+        }
+
+        if (A.stats && lane == 0) {
+            atomicAdd(A.stats + 0, (unsigned long long)pairs);
+            atomicAdd(A.stats + 1, (unsigned long long)scanned);
+            atomicAdd(A.stats + 2, (unsigned long long)skipped);
+            atomicAdd(A.stats + 3, (unsigned long long)pairs * D);
+        }
+
+        if (qpos < n) {
+            const int id = Jp->perm[qpos];
+            int32_t* eps_count = Jp->eps_count;
+            if (eps_count) {
+                eps_count[id] = cnt;
+                Jp->eps_mean[id] = cnt > 0 ? (float)(sum / (double)cnt) : 0.f;
+            }
+            if (KC > 0) {
+                int32_t* indeg = Jp->indeg;
+                int32_t* kids = Jp->knn_ids;
+                float* kdist = Jp->knn_dist;
+                float accm = 0.f;
+#pragma unroll
+                for (int j = 0; j < KS; ++j) {
+                    if (j >= KS - k) {
+                        const float dj = sqrtf(kd[j]);
+                        accm += dj;
+                        const int o = j - (KS - k);
+                        if (kids) kids[(int64_t)id * k + o] = kid[j];
+                        if (kdist) kdist[(int64_t)id * k + o] = dj;
+                        if (indeg) atomicAdd(indeg + kid[j], 1);
+                    }
+                }
+                float* kmean = Jp->knn_mean;
+                if (kmean) kmean[id] = accm / (float)k;
+                float* kth = Jp->knn_kth;
+                if (kth) kth[id] = kd[KS - 1];
+            }
+        }
+    }
+}
+
+template <int D>
+JoinFn join_mfma_pick_kc(int kc) {
+    switch (kc) {
+        case 0: return k_join_mfma<D, 0>;
+        case 5: return k_join_mfma<D, 5>;
+        case 10: return k_join_mfma<D, 10>;
+        case 20: return k_join_mfma<D, 20>;
+        case 32: return k_join_mfma<D, 32>;
+    }
+    return nullptr;
+}
+
+// Instantiation groups, one per translation unit.
+JoinFn join_mfma_pick_group0(int D, int kc);
+JoinFn join_mfma_pick_group1(int D, int kc);
+
+}  // namespace snaps

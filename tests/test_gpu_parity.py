@@ -78,7 +78,7 @@ def c0():
 
 @pytest.mark.parametrize("split", [1, 2, 4, 8])
 @pytest.mark.parametrize("mode", [1, 2])
-@pytest.mark.parametrize("filt", [1, 2])
+@pytest.mark.parametrize("filt", [1, 2, 3])
 def test_c0_parity(S, c0, split, mode, filt):
     x, k, eps = c0
     g = run_gpu(S, x, 0b111, k, float(eps), S.tuning(mode=mode, split=split, filter=filt))
@@ -131,7 +131,36 @@ def test_prefilter_is_bitwise_identical_to_direct_form(S, case):
         b = run_gpu(S, x, mask, k, eps, S.tuning(split=split, filter=2))
         for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
             np.testing.assert_array_equal(a[key], b[key], err_msg=f"{key} case={case} split={split}")
+        if split == 1:
+            m = run_gpu(S, x, mask, k, eps, S.tuning(split=1, filter=3))
+            for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+                np.testing.assert_array_equal(a[key], m[key], err_msg=f"{key} case={case} matrix cores")
     check_scores(b, run_oracle(x, mask, k, eps), k, eps, label=f"prefilter case {case}")
+
+
+@pytest.mark.parametrize("d", list(range(2, 17)))
+def test_matrix_core_prefilter_every_d_and_k(S, d):
+    """The matrix-core prefilter (every dimensionality and top-k capacity,
+    ragged last tiles, several jobs per call) gives the direct form's results
+    bit for bit, and meets the oracle."""
+    rng = np.random.default_rng(300 + d)
+    x = rng.random((777, 16)).astype(np.float32)
+    mask = int(sum(1 << f for f in rng.choice(16, size=d, replace=False)))
+    pop = S.Population.from_rows(x)
+    eps = 0.1 * math.sqrt(d)
+    ks = (1, 5, 10, 20, 32)
+    outs = {}
+    for filt in (1, 3):
+        jobs = [S.Job.alloc(pop, mask, k, eps) for k in ks]
+        S.snaps_outlier_scores(jobs, S.tuning(split=1, filter=filt))
+        torch.cuda.synchronize()
+        outs[filt] = [{key: getattr(j, key).cpu().numpy() for key in ("eps_count", "eps_mean", "indeg", "knn_mean",
+                                                                       "rank")} for j in jobs]
+    for k, a, b in zip(ks, outs[1], outs[3]):
+        for key in a:
+            np.testing.assert_array_equal(a[key], b[key], err_msg=f"{key} d={d} k={k}")
+    for k, b in zip((1, 10, 32), [outs[3][0], outs[3][2], outs[3][4]]):
+        check_scores(b, run_oracle(x, mask, k, eps), k, eps, label=f"matrix cores d={d} k={k}")
 
 
 def test_determinism(S, c0):
@@ -168,9 +197,10 @@ def test_duplicates_and_ties(S):
     base = (rng.integers(0, 4, size=(40, 3)) / 4.0).astype(np.float32)   # many exact duplicates
     x = np.concatenate([base, base, np.full((30, 3), 0.5, np.float32)])
     for k in (1, 3, 10, 32):
-        g = run_gpu(S, x, 0b111, k, 0.25)
         ora = run_oracle(x, 0b111, k, 0.25)
-        check_scores(g, ora, k, 0.25, label=f"dups k={k}")
+        for filt in (0, 3):
+            g = run_gpu(S, x, 0b111, k, 0.25, S.tuning(split=1, filter=filt))
+            check_scores(g, ora, k, 0.25, label=f"dups k={k} filter={filt}")
     m = 9
     same = np.full((m, 2), 0.25, np.float32)
     g = run_gpu(S, same, 0b11, 3, 0.01)
