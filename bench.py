@@ -35,11 +35,12 @@ if ROOT not in sys.path:
 
 METRIC = "object·subspace outlier scores/sec (batched vs plain, 1 GPU) + p50/p99 latency"
 UNIT = "object·subspace scores/s"
-PEAK_FP32_VECTOR = 157.3e12      # MI355X published FP32 vector peak, flop/s
+PEAK_FP32_MFMA = 157.3e12        # MI355X published dense FP32 matrix peak, flop/s
 PEAK_HBM = 8.0e12                # MI355X HBM3E, byte/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_join_c1_all_subspaces_hbm_traffic.md")
-JOIN_SOURCES = ["join_kernel.cuh", "join.hip", "join_inst0.hip", "join_inst1.hip", "join_inst2.hip",
-                "join_inst3.hip", "common.cuh", "snaps_internal.h"]
+JOIN_SOURCES = ["join_kernel.cuh", "join_mfma.cuh", "join.hip", "join_inst0.hip", "join_inst1.hip",
+                "join_inst2.hip", "join_inst3.hip", "join_mfma0.hip", "join_mfma1.hip", "common.cuh",
+                "snaps_internal.h"]
 
 
 def log(*a):
@@ -337,10 +338,10 @@ def main():
                                "(one job table, " + ("passes launched directly)" if a.eager else
                                                      "passes replayed as HIP graphs)"),
                    "n_objects": n, "n_subspaces": n_sp, "k": k, "subspaces_per_plan": chunk},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": stored_traffic(),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": "k_join (fused kNN + eps join), all instantiations",
+                     "kernel": "k_join_mfma (fused kNN + eps join, prefilter on fp32 MFMA), all instantiations",
                      "flops_per_pair": "3d", "avg_launch_ms": avg_launch_s * 1000.0, "launches": join_launches},
         "join": {"ms_per_step": join_ms / a.steps, "pairs_evaluated_per_step": pairs / a.steps,
                  "brute_force_pairs_per_step": brute_pairs / a.steps,

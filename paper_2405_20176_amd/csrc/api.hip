@@ -302,7 +302,9 @@ int launch_joins(const Meta& meta, const std::vector<ClassPlan>& plans, const Tu
                  hipStream_t s) {
     int64_t all_units = 0;
     for (const auto& p : plans) all_units += p.units;
-    const int xf_pref = tn.filter == 1 ? 0 : tn.filter == 3 ? 2 : 1;
+    // auto: the matrix-core prefilter (the vector-ALU one where the work unit
+    // spans several wavefronts)
+    const int xf_pref = tn.filter == 1 ? 0 : tn.filter == 2 ? 1 : 2;
     hipError_t fe = launch_fill_i32(meta.counters, meta.n_counters, 0, s);
     if (fe != hipSuccess) return hip_fail(fe, "counter reset");
     for (int c = 0; c < kNumClasses; ++c) {

@@ -23,7 +23,8 @@
 // the passing candidates of two queries in one candidate block; those bits
 // are written into the owning lanes' per-query candidate masks, whose union
 // is then walked candidate by candidate in ascending order (a
-// wavefront-uniform loop; the candidate row arrives by scalar loads).  Every
+// wavefront-uniform loop; the candidate row is read out of the operand
+// registers that already hold it, lane by lane).  Every
 // lane whose mask holds the candidate re-evaluates the exact direct-form
 // distance and updates its query's kNN list and eps sums exactly as k_join
 // does, in the same order, so the results are identical to both k_join
@@ -31,6 +32,8 @@
 #pragma once
 
 #include "join_kernel.cuh"
+
+#include <type_traits>
 
 namespace snaps {
 
@@ -55,9 +58,11 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
     constexpr int KSTEPS = (D + 1) / 2;      // coordinate steps; one more carries -lim and h
     constexpr float cq = (float)(2 * (8 * D + 24)) * 5.9604644775390625e-8f;
     __shared__ int s_unit, s_queue;
+    __shared__ uint2 s_mask[64];            // per-query candidate masks of one tile pair
 
     const int lane = threadIdx.x;
     const int half = lane >> 5;
+    s_mask[lane] = make_uint2(0u, 0u);
     const int col = lane & 31;
     const int home = blockIdx.x % kQueues;
     unsigned drained = 0;
@@ -140,9 +145,14 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
             return false;
         };
 
-        for (int s = 0; s < nt; ++s) {
-            const int t = spiral(t0, s, nt);
-            if (prune) {
+        // Next candidate tile of the walk whose box may hold a candidate
+        // (or -1 at the end); advances the walk position ws.
+        int ws = 0;
+        auto next_tile = [&]() -> int {
+            while (ws < nt) {
+                const int t = spiral(t0, ws, nt);
+                ++ws;
+                if (!prune) return t;
                 cptr<float> bx = boxes + (int64_t)t * 2 * DP;
                 float lb = 0.f;
 #pragma unroll
@@ -150,99 +160,136 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
                     const float g = fmaxf(fmaxf(bx[f] - q[f], q[f] - bx[DP + f]), 0.f);
                     lb = fmaf(g, g, lb);
                 }
-                if (!__any(lb <= thr)) {
-                    ++skipped;
-                    continue;
-                }
+                if (__any(lb <= thr)) return t;
+                ++skipped;
             }
+            return -1;
+        };
+        // Raw B operands of tile t (candidate rows 32 cb + col: lane half 0
+        // reads the even dimensions, half 1 the odd ones, then h), loaded
+        // through the global address space so that the loads are waited on
+        // only where the values are used, one tile later.
+        typedef const __attribute__((address_space(1))) float* gfloat;
+        const gfloat xg = (gfloat)xs_g;
+        // The candidate's id bits come along, so that the exact recheck can
+        // take a candidate's row from these registers (v_readlane) instead
+        // of memory.
+        auto load_b = [&](int t, float (&br)[2][KSTEPS + 2]) {
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const gfloat rowc = xg + (int64_t)(t * kTile + 32 * cb + col) * DP + half;
+#pragma unroll
+                for (int s2 = 0; s2 < KSTEPS; ++s2) br[cb][s2] = rowc[2 * s2];
+                br[cb][KSTEPS] = rowc[D - half];
+                br[cb][KSTEPS + 1] = rowc[D + 1 - half];
+            }
+        };
+
+        // Software pipeline: the next tile is chosen (with the threshold as
+        // it stands, which only ever shrinks, so the choice is conservative)
+        // and its operands requested before the current tile is screened.
+        // Two operand buffers, used alternately (no copies between them, so a
+        // tile's loads are waited on only when that tile is screened).
+        auto process = [&](int t, float (&br)[2][KSTEPS + 2]) {
             ++scanned;
             pairs += (long long)nq * min(kTile, n - t * kTile);
             const int cbase = t * kTile;
 
-            // B operands: candidate rows 32 cb + col of the tile, then (1, h).
-            float bv[2][KSTEPS + 1];
+            // B operands in place: 0 in the pad slot of an odd d, then (1, h)
+            // (the exact recheck reads only the coordinates and the id).
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                // lane half 0 reads the even dimensions, half 1 the odd ones
-                const float* rowc = xs_g + (int64_t)(cbase + 32 * cb + col) * DP + half;
-#pragma unroll
-                for (int s2 = 0; s2 < KSTEPS; ++s2) {
-                    const float v = rowc[2 * s2];
-                    bv[cb][s2] = (D % 2 == 1 && s2 == KSTEPS - 1 && half) ? 0.f : v;
-                }
-                const float h = rowc[D - half];
-                bv[cb][KSTEPS] = half ? h : 1.f;
+                if (D % 2 == 1 && half) br[cb][KSTEPS - 1] = 0.f;
+                br[cb][KSTEPS] = half ? br[cb][KSTEPS] : 1.f;
             }
-            f16v acc[2][2];
+            // One block row of queries at a time (32 accumulators live): the
+            // scores, a screen (most tile pairs have no passing pair), then the
+            // ballots, whose low and high halves lane 0 writes into the owning
+            // queries' rows of an LDS table of candidate masks.
+            unsigned u_lo = 0, u_hi = 0;
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+            for (int rb = 0; rb < 2; ++rb) {
+                f16v acc[2];
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
-                    acc[rb][cb] = f16v{};
+                    acc[cb] = f16v{};
 #pragma unroll
                     for (int s2 = 0; s2 <= KSTEPS; ++s2)
-                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][s2], bv[cb][s2], acc[rb][cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][s2], br[cb][s2], acc[cb], 0, 0, 0);
                 }
-
-            // Screen: does any pair of the tile pass?  (NaN pads never do.)
-            float mx = -INFINITY;
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+                float mx = -INFINITY;       // NaN pads never pass
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) mx = fmaxf(mx, acc[rb][cb][r]);
-            if (!__any(mx >= 0.f)) continue;
-
-            // Per-query candidate masks (this lane's query) and their union.
-            unsigned m_lo = 0, m_hi = 0;
-            unsigned u_lo = 0, u_hi = 0;
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+                    for (int r = 0; r < 16; ++r) mx = fmaxf(mx, acc[cb][r]);
+                if (!__any(mx >= 0.f)) continue;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const unsigned long long b0 = __ballot(acc[rb][0][r] >= 0.f);
-                    const unsigned long long b1 = __ballot(acc[rb][1][r] >= 0.f);
+                    const unsigned long long b0 = __ballot(acc[0][r] >= 0.f);
+                    const unsigned long long b1 = __ballot(acc[1][r] >= 0.f);
                     if (b0 | b1) {
                         const int i0 = acc_row(rb, r, 0);
-                        if (lane == i0) {
-                            m_lo = (unsigned)b0;
-                            m_hi = (unsigned)b1;
-                        }
-                        if (lane == i0 + 4) {
-                            m_lo = (unsigned)(b0 >> 32);
-                            m_hi = (unsigned)(b1 >> 32);
+                        if (lane == 0) {
+                            s_mask[i0] = make_uint2((unsigned)b0, (unsigned)b1);
+                            s_mask[i0 + 4] = make_uint2((unsigned)(b0 >> 32), (unsigned)(b1 >> 32));
                         }
                         u_lo |= (unsigned)b0 | (unsigned)(b0 >> 32);
                         u_hi |= (unsigned)b1 | (unsigned)(b1 >> 32);
                     }
                 }
-            unsigned long long un = ((unsigned long long)u_hi << 32) | u_lo;
-            if (un) {
+            }
+            if (u_lo | u_hi) {
+                const uint2 mine2 = s_mask[lane];
+                s_mask[lane] = make_uint2(0u, 0u);
                 bool moved = false;
-                while (un) {
-                    const int j = __builtin_ctzll(un);
-                    un &= un - 1;
-                    const int c = cbase + j;
-                    cptr<f4v> pv = (cptr<f4v>)(xs + (int64_t)c * DP);
-                    f4v blk[DP / 4];
+                // Candidates of block cb with a passing pair, ascending; the row
+                // of candidate 32 cb + jj: even dimensions in lane jj, odd ones
+                // in lane jj + 32 of the operand registers.
+                auto recheck = [&](auto cbc, unsigned um, unsigned mine) {
+                    constexpr int cb = decltype(cbc)::value;
+                    while (um) {
+                        const int jj = __builtin_ctz(um);
+                        um &= um - 1;
+                        const int c = cbase + 32 * cb + jj;
+                        float pr[D];
 #pragma unroll
-                    for (int v = 0; v < DP / 4; ++v) blk[v] = pv[v];
-#define PV(f) blk[(f) >> 2][(f) & 3]
-                    const unsigned bit = j < 32 ? (m_lo >> j) : (m_hi >> (j - 32));
-                    if ((bit & 1u) && c != qpos) {
-                        float dd = 0.f;
+                        for (int f = 0; f < D; ++f)
+                            pr[f] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(br[cb][f >> 1]),
+                                                                             jj + 32 * (f & 1)));
+                        const int cid = __builtin_amdgcn_readlane(__float_as_int(br[cb][KSTEPS + 1]), jj);
+                        if (((mine >> jj) & 1u) && c != qpos) {
+                            float dd = 0.f;
 #pragma unroll
-                        for (int f = 0; f < D; ++f) {
-                            const float tq = q[f] - PV(f);
-                            dd = fmaf(tq, tq, dd);
+                            for (int f = 0; f < D; ++f) {
+                                const float tq = q[f] - pr[f];
+                                dd = fmaf(tq, tq, dd);
+                            }
+                            if (dd <= thr) moved |= take(dd, cid);
                         }
-                        if (dd <= thr) moved |= take(dd, __float_as_int(PV(D + 1)));
                     }
-#undef PV
-                }
+                };
+                recheck(std::integral_constant<int, 0>{}, u_lo, mine2.x);
+                recheck(std::integral_constant<int, 1>{}, u_hi, mine2.y);
                 if (__any(moved)) refresh_limits();
             }
+        };
+        // The loads are issued unconditionally (the last prefetch re-reads the
+        // current tile) so that every path waits on the same load count.
+        // A scheduling barrier after each prefetch keeps the compiler from
+        // hoisting the other buffer's uses (and their waits) above it.
+        float ba[2][KSTEPS + 2], bb[2][KSTEPS + 2];
+        int t = next_tile();
+        load_b(t >= 0 ? t : t0, ba);
+        while (t >= 0) {
+            const int tn = next_tile();
+            load_b(tn >= 0 ? tn : t, bb);
+            __builtin_amdgcn_sched_barrier(0);
+            process(t, ba);
+            if (tn < 0) break;
+            t = next_tile();
+            load_b(t >= 0 ? t : tn, ba);
+            __builtin_amdgcn_sched_barrier(0);
+            process(tn, bb);
         }
 
         if (A.stats && lane == 0) {
