@@ -339,7 +339,7 @@ def main():
                                                      "passes replayed as HIP graphs)"),
                    "n_objects": n, "n_subspaces": n_sp, "k": k, "subspaces_per_plan": chunk},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": stored_traffic(),
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": stored_traffic(),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_join_mfma (fused kNN + eps join, prefilter on fp32 MFMA), all instantiations",
                      "flops_per_pair": "3d", "avg_launch_ms": avg_launch_s * 1000.0, "launches": join_launches},
