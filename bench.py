@@ -208,7 +208,7 @@ class _Eager:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=0, help="subspaces per batched plan (0: all in one)")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving run length (0: skip)")
@@ -288,18 +288,26 @@ def main():
     log(f"{len(chunks)} plan(s) of 3 {'eager passes' if a.eager else 'graphs'} built in {time.perf_counter() - t_plan:.1f} s, workspace "
         f"{ws_total / 2**30:.2f} GiB, outputs {n_sp * n * 32 / 2**30:.1f} GiB")
 
-    def step(events=None):
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def step(marks=None):
+        """One step; with marks, events around each pass of each plan
+        (start, after index, after join, after rank)."""
         for _, (p_index, p_join, p_rank) in plans:
+            m = [ev()] if marks is not None else None
             p_index.launch(stream)
-            if events is not None:
-                ev0 = torch.cuda.Event(enable_timing=True)
-                ev1 = torch.cuda.Event(enable_timing=True)
-                ev0.record(stream)
+            if m is not None:
+                m.append(ev())
             p_join.launch(stream)
-            if events is not None:
-                ev1.record(stream)
-                events.append((ev0, ev1))
+            if m is not None:
+                m.append(ev())
             p_rank.launch(stream)
+            if m is not None:
+                m.append(ev())
+                marks.append(m)
 
     for w in range(a.warmup):
         t = time.perf_counter()
@@ -308,17 +316,23 @@ def main():
         log(f"warmup {w}: {time.perf_counter() - t:.2f} s")
 
     stats.zero_()
-    events = []
+    marks = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
-        step(events)
+        step(marks)
         log(f"step {i} enqueued")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1000.0 / a.steps
     value = n * n_sp / (ms_per_step / 1000.0)
-    join_ms = sum(e0.elapsed_time(e1) for e0, e1 in events)
+    per_plan = len(plans)
+    step_ms = [sum(marks[i * per_plan + j][0].elapsed_time(marks[i * per_plan + j][3]) for j in range(per_plan))
+               for i in range(a.steps)]
+    index_ms = sum(m[0].elapsed_time(m[1]) for m in marks)
+    join_ms = sum(m[1].elapsed_time(m[2]) for m in marks)
+    rank_ms = sum(m[2].elapsed_time(m[3]) for m in marks)
+    results_per_step = float(n_sp) * n * k + float(out_cnt.sum(dtype=torch.int64).item())
     st = stats.cpu().numpy().astype(np.float64)
     pairs, scanned, skipped, pair_dims = st
     brute_pairs = a.steps * float(n) * n * n_sp
@@ -343,8 +357,13 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_join_mfma (fused kNN + eps join, prefilter on fp32 MFMA), all instantiations",
                      "flops_per_pair": "3d", "avg_launch_ms": avg_launch_s * 1000.0, "launches": join_launches},
+        "step_ms": {"median": float(np.median(step_ms)), "min": float(min(step_ms)), "max": float(max(step_ms)),
+                    "each": step_ms, "clock": "HIP events on the library stream around each whole step"},
+        "passes_ms_per_step": {"index": index_ms / a.steps, "join": join_ms / a.steps, "rank": rank_ms / a.steps},
         "join": {"ms_per_step": join_ms / a.steps, "pairs_evaluated_per_step": pairs / a.steps,
                  "brute_force_pairs_per_step": brute_pairs / a.steps,
+                 "results_per_step": results_per_step,
+                 "candidates_per_result": pairs / a.steps / results_per_step,
                  "tiles_scanned": scanned / a.steps, "tiles_skipped": skipped / a.steps,
                  "evals_per_s": pairs / (join_ms / 1000.0)},
     }

@@ -119,7 +119,12 @@ typedef struct {
     int32_t mq;             /* 0 auto, else waves per workgroup that take consecutive query tiles
                                of one job and walk the same candidate tiles in lockstep: 1, 2,
                                4 or 8 (1 = off).  Used only when split is 1. */
-    int32_t reserved[2];    /* must be 0 */
+    int32_t index_sort;     /* 0 auto (2), 1 object id packed under the cell key in 32 bits and
+                               sorted in one workgroup's LDS (coarser cells; jobs with n above
+                               32,768 always use 2), 2 device-wide radix sort of full 32-bit
+                               cell keys with the id as payload.  Results do not depend on it
+                               beyond the summation order of the eps means. */
+    int32_t reserved;       /* must be 0 */
     uint64_t* stats;        /* optional device uint64[4], accumulated (never cleared) by the
                                join pass: [0] query-candidate pairs evaluated, [1] candidate
                                tiles scanned, [2] candidate tiles skipped, [3] pairs evaluated

@@ -89,8 +89,8 @@ int check_tuning(const snaps_tuning* t) {
     if (!(t->mq == 0 || t->mq == 1 || t->mq == 2 || t->mq == 4 || t->mq == 8))
         return fail(SNAPS_EINVAL, "tuning.mq must be 0, 1, 2, 4 or 8");
     if (t->mq > 1 && t->split > 1) return fail(SNAPS_EINVAL, "tuning.mq and tuning.split cannot both exceed 1");
-    for (int i = 0; i < 2; ++i)
-        if (t->reserved[i] != 0) return fail(SNAPS_EINVAL, "tuning.reserved must be zero");
+    if (t->index_sort < 0 || t->index_sort > 2) return fail(SNAPS_EINVAL, "tuning.index_sort must be 0, 1 or 2");
+    if (t->reserved != 0) return fail(SNAPS_EINVAL, "tuning.reserved must be zero");
     return SNAPS_OK;
 }
 
@@ -121,7 +121,8 @@ int device_info(DeviceInfo* out) {
 // What one job needs, decided on the host.
 struct JobPlan {
     int32_t n, d, k, kc, ntiles, nchunks;
-    bool large;              // index and ranks through the device-wide radix sort
+    bool large;              // index through the device-wide radix sort (full 32-bit cell keys)
+    bool large_rank;         // ranks through the device-wide radix sort (n above one LDS)
     bool rank;               // rank scratch reserved
     size_t xs_off, perm_off, box_off;
     size_t ihist_off, acc_off, sel_off;          // large index scratch
@@ -129,7 +130,13 @@ struct JobPlan {
     size_t bytes;
 };
 
-JobPlan plan_job(int64_t n, int d, int k, bool with_rank, bool force_large = false) {
+// Index sort of a job: kIndexAuto (the device-wide radix sort), kIndexPacked
+// (object id packed under the cell key in 32 bits and sorted in one LDS;
+// coarser cells, only for n within one LDS) or kIndexRadix.  force_large also
+// ranks through the device-wide path (the serving state keeps its sorted keys).
+constexpr int kIndexAuto = 0, kIndexPacked = 1, kIndexRadix = 2;
+
+JobPlan plan_job(int64_t n, int d, int k, bool with_rank, int index_sort = kIndexAuto, bool force_large = false) {
     JobPlan p{};
     p.n = (int32_t)n;
     p.d = d;
@@ -137,7 +144,8 @@ JobPlan plan_job(int64_t n, int d, int k, bool with_rank, bool force_large = fal
     p.kc = kc_class(k);
     p.ntiles = (int32_t)((n + kTile - 1) / kTile);
     p.nchunks = (int32_t)((n + kRadixChunk - 1) / kRadixChunk);
-    p.large = force_large || n > kLdsSortMax;
+    p.large_rank = force_large || n > kLdsSortMax;
+    p.large = p.large_rank || index_sort != kIndexPacked;
     p.rank = with_rank;
     const size_t rows = (size_t)p.ntiles * kTile;
     const int dp = row_stride(d);
@@ -157,7 +165,7 @@ JobPlan plan_job(int64_t n, int d, int k, bool with_rank, bool force_large = fal
         off += align_up(2 * kMaxD * sizeof(double));
         p.sel_off = off;
         off += align_up(3 * kMaxIndexDims * sizeof(float));
-        if (with_rank) {
+        if (with_rank && p.large_rank) {
             p.rkey_off = off;
             off += align_up(4 * rows * sizeof(uint32_t));
             p.rpong_off = off;
@@ -252,6 +260,7 @@ DevJob make_devjob(const snaps_population* P, uint32_t mask, const JobPlan& p, f
         j.idbits = std::max(1, ceil_log2(p.n));
         j.bits = std::max(1, (32 - j.idbits) / c);
     }
+    j.flags = (p.large ? kJobRadixIndex : 0) | (p.large_rank ? kJobRadixRank : 0);
     if (tn.mode == 1) j.prune = 0;
     else if (tn.mode == 2) j.prune = 1;
     else j.prune = p.d <= 10 ? 1 : 0;
@@ -359,10 +368,8 @@ void count_large(const std::vector<RunJob>& jobs, int* n_large, int* n_lrank) {
     *n_large = 0;
     *n_lrank = 0;
     for (const auto& j : jobs) {
-        if (j.plan.large) {
-            ++*n_large;
-            if (j.rank) ++*n_lrank;
-        }
+        if (j.plan.large) ++*n_large;
+        if (j.plan.large_rank && j.rank) ++*n_lrank;
     }
 }
 
@@ -506,7 +513,7 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         g.nchunks = p.nchunks;
         iseg.push_back(g);
         ichunk.push_back(ichunk.back() + p.nchunks);
-        if (jobs[i].rank) {
+        if (jobs[i].rank && p.large_rank) {
             LargeRank R{};
             R.job = i;
             R.nchunks = p.nchunks;
@@ -637,10 +644,11 @@ size_t snaps_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t k) {
     else if (k < 1 || k > n - 1 || k > kMaxK) return 0;
     if (op != SNAPS_OP_KNN && op != SNAPS_OP_EPS && op != SNAPS_OP_SCORES) return 0;
     const JobPlan p = plan_job(n, d, k, op == SNAPS_OP_SCORES);
-    return meta_layout(1, p.large ? 1 : 0, (p.large && op == SNAPS_OP_SCORES) ? 1 : 0).bytes + p.bytes;
+    return meta_layout(1, p.large ? 1 : 0, (p.large_rank && op == SNAPS_OP_SCORES) ? 1 : 0).bytes + p.bytes;
 }
 
-static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, std::vector<RunJob>* out) {
+static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune, std::vector<RunJob>* out) {
+    const int index_sort = tune ? tune->index_sort : kIndexAuto;
     if (n_jobs < 1) return fail(SNAPS_EINVAL, "n_jobs must be >= 1");
     if (!jobs) return fail(SNAPS_EINVAL, "jobs is NULL");
     out->clear();
@@ -659,7 +667,7 @@ static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, std::vector<RunJo
         r.pop = j.pop;
         r.mask = j.mask;
         r.eps = j.eps;
-        r.plan = plan_job(j.pop->n, popcount32(j.mask), j.k, j.rank != nullptr);
+        r.plan = plan_job(j.pop->n, popcount32(j.mask), j.k, j.rank != nullptr, index_sort);
         r.eps_count = j.out.eps_count;
         r.eps_mean = j.out.eps_mean;
         r.indeg = j.out.indeg;
@@ -673,7 +681,7 @@ static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, std::vector<RunJo
 size_t snaps_outlier_scores_workspace(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune) {
     std::vector<RunJob> rj;
     if (check_tuning(tune) != SNAPS_OK) return 0;
-    if (collect_jobs(jobs, n_jobs, &rj) != SNAPS_OK) return 0;
+    if (collect_jobs(jobs, n_jobs, tune, &rj) != SNAPS_OK) return 0;
     return run_workspace(rj);
 }
 
@@ -720,7 +728,7 @@ int snaps_outlier_scores(const snaps_job* jobs, int32_t n_jobs, const snaps_tuni
     int rc = check_tuning(tune);
     if (rc != SNAPS_OK) return rc;
     std::vector<RunJob> rj;
-    rc = collect_jobs(jobs, n_jobs, &rj);
+    rc = collect_jobs(jobs, n_jobs, tune, &rj);
     if (rc != SNAPS_OK) return rc;
     return run(rj, resolve_tune(tune), ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
@@ -806,7 +814,7 @@ int snaps_plan_create(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning*
     int rc = check_tuning(tune);
     if (rc != SNAPS_OK) return rc;
     std::vector<RunJob> rj;
-    rc = collect_jobs(jobs, n_jobs, &rj);
+    rc = collect_jobs(jobs, n_jobs, tune, &rj);
     if (rc != SNAPS_OK) return rc;
     const Tune tn = resolve_tune(tune);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -872,7 +880,7 @@ struct ServeLayout {
 
 ServeLayout serve_layout(int64_t n, int d, int k) {
     ServeLayout L{};
-    L.plan = plan_job(n, d, k, true, true);
+    L.plan = plan_job(n, d, k, true, kIndexRadix, true);
     const size_t rows = (size_t)L.plan.ntiles * kTile;
     size_t off = 0;
     auto take = [&](size_t b) {

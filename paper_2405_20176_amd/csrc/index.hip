@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kSortThreads) void k_index_sort(IndexArgs A) {
         J = A.meta.table[blockIdx.x];
     }
     if (blockIdx.x == 0 && (int)threadIdx.x < A.meta.n_counters) A.meta.counters[threadIdx.x] = 0;
-    if (J.n > kLdsSortMax) return;           // indexed by the device-wide path
+    if (J.flags & kJobRadixIndex) return;    // indexed by the device-wide path
 
     const int n = J.n;
     const int d = J.d;

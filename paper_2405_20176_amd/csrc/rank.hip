@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rank(RankLaunch L) {
     __shared__ uint32_t buf[kLdsSortMax];
     __shared__ int tmp[17];
     const DevJob J = L.seed ? L.single : L.a.table[blockIdx.x];
-    if (J.rank == nullptr || J.n > kLdsSortMax) return;   // large jobs: device-wide path
+    if (J.rank == nullptr || (J.flags & kJobRadixRank)) return;   // ranked by the device-wide path
     const int metric = blockIdx.y;
     const int n = J.n;
     const int tid = threadIdx.x;

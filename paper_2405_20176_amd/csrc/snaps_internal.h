@@ -22,6 +22,11 @@ __host__ __device__ constexpr int row_stride(int d) { return ((d + 2 + 3) / 4) *
 
 // One (population, subspace) job as the kernels see it.  Lives in device
 // memory (the job table inside the caller's workspace).
+// DevJob.flags: which jobs the device-wide radix sort indexes / ranks (the
+// others are sorted inside one workgroup's LDS).
+constexpr int kJobRadixIndex = 1;
+constexpr int kJobRadixRank = 2;
+
 struct DevJob {
     const float* cols;       // population, cols[f * ld + i]
     int64_t ld;
@@ -35,7 +40,7 @@ struct DevJob {
     int32_t idbits;          // bits of the packed sort key holding the object id
     int32_t bits;            // Morton bits per indexed dimension
     int32_t prune;           // 1: skip candidate tiles whose box is out of reach
-    int32_t pad0;
+    int32_t flags;           // kJobRadixIndex | kJobRadixRank: passes taken by the device-wide sort
     float* xs;               // [ntiles*64][row_stride(d)] coordinates in index order (+ norm)
     int32_t* perm;           // [ntiles*64] index position -> object id (pads: INT32_MAX)
                              // (the id is also stored in slot d + 1 of each xs row)

@@ -51,7 +51,7 @@ class c_job(ctypes.Structure):
 class c_tuning(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("split", ctypes.c_int32), ("index_dims", ctypes.c_int32),
                 ("filter", ctypes.c_int32), ("passes", ctypes.c_int32), ("mq", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2), ("stats", ctypes.c_void_p)]
+                ("index_sort", ctypes.c_int32), ("reserved", ctypes.c_int32), ("stats", ctypes.c_void_p)]
 
 
 PASS_INDEX, PASS_JOIN, PASS_RANK = 1, 2, 4
@@ -152,12 +152,13 @@ class Population:
 
 
 def tuning(mode=0, split=0, index_dims=0, filter=0, passes=0, stats: Optional[torch.Tensor] = None,
-           mq=0) -> c_tuning:
+           mq=0, index_sort=0) -> c_tuning:
     """Tuning record; ``stats`` is an optional int64 CUDA tensor of 4
     accumulated join counters (pairs evaluated, tiles scanned, tiles
     skipped, pairs x dimensionality)."""
     t = c_tuning()
     t.mode, t.split, t.index_dims, t.filter, t.passes, t.mq = mode, split, index_dims, filter, passes, mq
+    t.index_sort = index_sort
     t.stats = None if stats is None else stats.data_ptr()
     return t
 

@@ -110,6 +110,15 @@ def test_outlier_scores_validation(lib):
     t = c_tuning()
     t.split = 3
     assert lib.snaps_outlier_scores(ctypes.byref(job), 1, ctypes.byref(t), None, 0, None) == -1
+    for field, value in (("index_sort", 3), ("reserved", 1), ("filter", 4), ("mq", 3)):
+        t = c_tuning()
+        setattr(t, field, value)
+        assert lib.snaps_outlier_scores(ctypes.byref(job), 1, ctypes.byref(t), None, 0, None) == -1, field
+    # the packed LDS index needs no device-wide sort scratch
+    tp, tr = c_tuning(), c_tuning()
+    tp.index_sort, tr.index_sort = 1, 2
+    assert (lib.snaps_outlier_scores_workspace(ctypes.byref(job), 1, ctypes.byref(tp))
+            < lib.snaps_outlier_scores_workspace(ctypes.byref(job), 1, ctypes.byref(tr)))
     t = c_tuning()
     need = lib.snaps_outlier_scores_workspace(ctypes.byref(job), 1, ctypes.byref(t))
     assert need > 0

@@ -163,6 +163,28 @@ def test_matrix_core_prefilter_every_d_and_k(S, d):
         check_scores(b, run_oracle(x, mask, k, eps), k, eps, label=f"matrix cores d={d} k={k}")
 
 
+@pytest.mark.parametrize("d", [2, 5, 8, 12])
+def test_index_sorts_agree(S, d):
+    """The packed-key LDS index and the full-key device-wide index order the
+    objects differently; every result that does not depend on the summation
+    order is identical, eps means agree to float32 rounding, and both meet
+    the oracle."""
+    rng = np.random.default_rng(900 + d)
+    x = rng.random((4000, 16)).astype(np.float32)
+    mask = int(sum(1 << f for f in rng.choice(16, size=d, replace=False)))
+    eps = 0.09 * math.sqrt(d)
+    a = run_gpu(S, x, mask, 10, eps, S.tuning(index_sort=1))
+    b = run_gpu(S, x, mask, 10, eps, S.tuning(index_sort=2))
+    for key in ("eps_count", "indeg", "knn_mean"):
+        np.testing.assert_array_equal(a[key], b[key], err_msg=key)
+    np.testing.assert_allclose(a["eps_mean"], b["eps_mean"], rtol=1e-6)
+    for r in (0, 2, 3):
+        np.testing.assert_array_equal(a["rank"][r], b["rank"][r])
+    ora = run_oracle(x, mask, 10, eps)
+    check_scores(a, ora, 10, eps, label=f"packed index d={d}")
+    check_scores(b, ora, 10, eps, label=f"radix index d={d}")
+
+
 def test_determinism(S, c0):
     x, k, eps = c0
     a = run_gpu(S, x, 0b111, k, float(eps))
