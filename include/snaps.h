@@ -94,6 +94,9 @@ typedef struct {
     snaps_scores out;       /* required */
     int32_t* rank;          /* [4][n] device or NULL: dense ranks of (eps_count, eps_mean,
                                indeg, knn_mean), 0 = most outlying */
+    float* ensemble;        /* [n] device or NULL (needs rank): the mean of the object's four
+                               ranks, the average over the four methods that Sec. 5 suggests
+                               for objects outlying in several of them; lower = more outlying */
 } snaps_job;
 
 /* Passes of snaps_outlier_scores (snaps_tuning.passes). */
@@ -271,6 +274,38 @@ typedef struct {
  * are set to -1, the means to NaN, ranks are left untouched).  At most 2^31
  * alerts per call.  Asynchronous on stream. */
 int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Sampled-distance search radius (paper Sec. 3.5.3).  The paper picks the
+ * radii eps_min and eps_max of its eps grid -- the radii at which the mean
+ * number of neighbours per object (the selectivity s) reaches about 0.1 % and
+ * 15 % of the population -- by sampling: the distances of a sample of objects
+ * to every other object give the relation between a radius and the mean
+ * neighbour count.  For each target count T this computes the midpoint
+ * between the r-th smallest of the sample's m (n - 1) Euclidean distances,
+ * r = round(T m) (ties to even), and the next one: the radius at which the
+ * sample's mean neighbour count reaches T.  Distances are float32 (direct
+ * form); the selection over them is exact.  The sample is an input: the
+ * caller draws it (distinct object ids). */
+#define SNAPS_MAX_EPS_TARGETS 8
+typedef struct {
+    const snaps_population* pop;
+    uint32_t mask;              /* subspace */
+    int32_t m;                  /* sample size, 1..n */
+    const int32_t* sample;      /* [m] device: distinct object ids in [0, n); ids outside are
+                                   ignored (the radius is NaN if too few distances remain) */
+    int32_t n_targets;          /* 1..SNAPS_MAX_EPS_TARGETS */
+    float target[SNAPS_MAX_EPS_TARGETS];   /* mean neighbour counts, with 1 <= round(T m)
+                                              <= m (n - 1) - 1 */
+    float* eps;                 /* [n_targets] device output */
+} snaps_eps_job;
+
+/* Workspace bytes of snaps_eps_sample for these jobs (0 if a job is invalid). */
+size_t snaps_eps_sample_workspace(const snaps_eps_job* jobs, int32_t n_jobs);
+/* Radii of every job (any mix of populations and subspaces; m (n - 1) < 2^32
+ * per job, at most 2^31 - 1 sample objects per call).  The job list is host
+ * memory, read during the call.  Asynchronous on stream. */
+int snaps_eps_sample(const snaps_eps_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

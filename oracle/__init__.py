@@ -19,9 +19,11 @@ from .snaps_oracle import (  # noqa: F401
     dense_rank,
     rank_keys,
     rank_metrics,
+    ensemble,
     outlier_scores,
     alert_scores,
     selectivity,
     eps_exact_mean_count,
+    eps_from_sample,
     eps_sampled_mean_count,
 )

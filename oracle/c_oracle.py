@@ -104,7 +104,7 @@ def outlier_scores(X, k: int, eps: float, nthreads: int = 0, band=None) -> dict:
     kmean = r["knn_dist"].sum(axis=1) / k
     ranks = O.rank_metrics(cnt, mean, deg, kmean)
     out = dict(knn_ids=r["knn_ids"], knn_dist=r["knn_dist"], knn_next=r["knn_next"],
-               eps_count=cnt, eps_mean=mean, indeg=deg, knn_mean=kmean, rank=ranks)
+               eps_count=cnt, eps_mean=mean, indeg=deg, knn_mean=kmean, rank=ranks, ensemble=O.ensemble(ranks))
     if band is not None:
         out["band"] = r["band"]
     return out

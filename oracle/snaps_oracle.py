@@ -143,6 +143,13 @@ def rank_metrics(eps_count, eps_mean, indeg, knn_mean) -> np.ndarray:
     return np.stack([dense_rank(k) for k in rank_keys(eps_count, eps_mean, indeg, knn_mean)])
 
 
+def ensemble(ranks: np.ndarray) -> np.ndarray:
+    """Mean of an object's four dense ranks, the average over the four
+    methods that Sec. 5 suggests for finding objects that are outlying in
+    several of them (lower = more outlying)."""
+    return np.asarray(ranks, dtype=np.float64).mean(axis=0)
+
+
 def outlier_scores(X: np.ndarray, k: int, eps: float) -> dict:
     """All four metrics and their ranks for one (population, space) job."""
     X = np.asarray(X, dtype=np.float64)
@@ -153,7 +160,7 @@ def outlier_scores(X: np.ndarray, k: int, eps: float) -> dict:
     kmean = dist.sum(axis=1) / k
     ranks = rank_metrics(count, mean, deg, kmean)
     return dict(knn_ids=ids, knn_dist=dist, knn_next=nxt, eps_count=count,
-                eps_mean=mean, indeg=deg, knn_mean=kmean, rank=ranks)
+                eps_mean=mean, indeg=deg, knn_mean=kmean, rank=ranks, ensemble=ensemble(ranks))
 
 
 def alert_scores(P: np.ndarray, A: np.ndarray, k: int, eps: float, pop: dict | None = None) -> dict:
@@ -215,17 +222,15 @@ def eps_exact_mean_count(X: np.ndarray, target: int) -> np.float32:
     return np.float32(0.5 * (d[m - 1] + d[m]))
 
 
-def eps_sampled_mean_count(X: np.ndarray, target: float, m: int, seed: int) -> np.float32:
-    """Sampled-distance choice of eps (the lightweight method the paper uses
-    to pick a search radius for a target selectivity, Sec. 3.5.3): draw ``m``
-    seeded objects, compute their distances to every other object, and take
-    the radius at which the sample's mean neighbour count reaches
-    ``target`` (midpoint between that distance and the next), as float32."""
+def eps_from_sample(X: np.ndarray, sample: np.ndarray, target: float) -> np.float32:
+    """Sampled-distance choice of eps (Sec. 3.5.3) for a given sample: the
+    distances of the ``sample`` objects to every other object, and the radius
+    at which the sample's mean neighbour count reaches ``target`` (the
+    midpoint between the round(target * m)-th smallest of them and the next),
+    as float32."""
     X = np.asarray(X, dtype=np.float64)
-    n = X.shape[0]
-    m = min(m, n)
-    rng = np.random.default_rng(seed)
-    sample = np.sort(rng.choice(n, size=m, replace=False))
+    sample = np.asarray(sample, dtype=np.int64)
+    m = sample.size
     D = pair_distances(X[sample], X)
     D[np.arange(m), sample] = np.inf
     flat = D.ravel()
@@ -233,3 +238,12 @@ def eps_sampled_mean_count(X: np.ndarray, target: float, m: int, seed: int) -> n
     r = max(1, min(r, flat.size - 1))
     part = np.partition(flat, (r - 1, r))
     return np.float32(0.5 * (part[r - 1] + part[r]))
+
+
+def eps_sampled_mean_count(X: np.ndarray, target: float, m: int, seed: int) -> np.float32:
+    """eps_from_sample with ``m`` seeded distinct objects (sorted ids)."""
+    n = np.asarray(X).shape[0]
+    m = min(m, n)
+    rng = np.random.default_rng(seed)
+    sample = np.sort(rng.choice(n, size=m, replace=False))
+    return eps_from_sample(X, sample, target)

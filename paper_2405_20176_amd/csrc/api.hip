@@ -4,6 +4,7 @@
 #include "../../include/snaps.h"
 
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -359,6 +360,7 @@ struct RunJob {
     int32_t* indeg;
     float* knn_mean;
     int32_t* rank;
+    float* ensemble;
     int32_t* knn_ids;
     float* knn_dist;
     float* knn_kth;
@@ -427,6 +429,7 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         j.indeg = r.indeg;
         j.knn_mean = r.knn_mean;
         j.rank = r.rank;
+        j.ensemble = r.rank ? r.ensemble : nullptr;
         j.knn_ids = r.knn_ids;
         j.knn_dist = r.knn_dist;
         j.knn_kth = r.knn_kth;
@@ -614,6 +617,12 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
                               reinterpret_cast<const SortSeg*>(base + ml.rseg),
                               reinterpret_cast<const int32_t*>(base + ml.rsegchunk), rsegchunk.back(), s);
         if (e != hipSuccess) return hip_fail(e, "large rank launch");
+        bool any_ens = false;
+        for (const auto& j : jobs) any_ens |= (j.rank != nullptr && j.ensemble != nullptr);
+        if (any_ens) {
+            e = launch_ensemble(meta.table, n_jobs, meta.tile_prefix, (int32_t)total_tiles, s);
+            if (e != hipSuccess) return hip_fail(e, "ensemble launch");
+        }
     }
     return SNAPS_OK;
 }
@@ -673,6 +682,8 @@ static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, const snaps_tunin
         r.indeg = j.out.indeg;
         r.knn_mean = j.out.knn_mean;
         r.rank = j.rank;
+        if (j.ensemble && !j.rank) return fail(SNAPS_EINVAL, "job %d: the ensemble output needs the rank output", i);
+        r.ensemble = j.ensemble;
         out->push_back(r);
     }
     return SNAPS_OK;
@@ -1040,6 +1051,138 @@ int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, i
         aa.alert_prefix[nb] = (int32_t)alerts;
         hipError_t e = launch_alerts(d, kc, aa, s);
         if (e != hipSuccess) return hip_fail(e, "alert scoring launch");
+    }
+    return SNAPS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ eps sampler
+
+namespace {
+
+struct EpsPlan {
+    int n_jobs = 0;
+    std::vector<int> d;                 // per job
+    std::vector<std::array<uint32_t, kMaxEpsTargets>> rank;
+    size_t table = 0, prefix = 0, hist = 0, state = 0, bytes = 0;
+};
+
+int plan_eps(const snaps_eps_job* jobs, int32_t n_jobs, EpsPlan* p) {
+    if (n_jobs < 1 || !jobs) return fail(SNAPS_EINVAL, "need at least one eps job");
+    p->n_jobs = n_jobs;
+    p->d.resize(n_jobs);
+    p->rank.resize(n_jobs);
+    int64_t blocks = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const snaps_eps_job& j = jobs[i];
+        int rc = check_population(j.pop, j.mask);
+        if (rc != SNAPS_OK) return fail(rc, "eps job %d: %s", i, g_error.c_str());
+        const int64_t n = j.pop->n;
+        if (j.m < 1 || j.m > n) return fail(SNAPS_EINVAL, "eps job %d: sample size %d not in [1, n]", i, j.m);
+        if (!j.sample || !j.eps) return fail(SNAPS_EINVAL, "eps job %d: sample and eps are required", i);
+        if (j.n_targets < 1 || j.n_targets > kMaxEpsTargets)
+            return fail(SNAPS_EINVAL, "eps job %d: n_targets must be in [1, %d]", i, kMaxEpsTargets);
+        const int64_t pairs = (int64_t)j.m * (n - 1);
+        if (pairs >= (int64_t)1 << 32)
+            return fail(SNAPS_EUNSUPPORTED, "eps job %d: m (n - 1) = %lld sample distances exceed 2^32", i,
+                        (long long)pairs);
+        for (int t = 0; t < j.n_targets; ++t) {
+            const double tt = j.target[t];
+            if (!(tt > 0.0) || !std::isfinite(tt)) return fail(SNAPS_EINVAL, "eps job %d: target %d must be > 0", i, t);
+            const double r = std::nearbyint(tt * (double)j.m);     // round half to even
+            if (r < 1.0 || r > (double)(pairs - 1))
+                return fail(SNAPS_EINVAL, "eps job %d: round(target m) = %.0f not in [1, m (n - 1) - 1]", i, r);
+            p->rank[i][t] = (uint32_t)r;
+        }
+        p->d[i] = popcount32(j.mask);
+        blocks += j.m;
+    }
+    if (blocks > INT32_MAX) return fail(SNAPS_EUNSUPPORTED, "more than 2^31 - 1 sample objects in one call");
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += align_up(b);
+        return o;
+    };
+    p->table = take((size_t)n_jobs * sizeof(EpsJob));
+    p->prefix = take((size_t)(n_jobs + kMaxD + 2) * sizeof(int32_t));
+    p->hist = take((size_t)n_jobs * kMaxEpsTargets * 256 * sizeof(uint32_t));
+    p->state = take((size_t)n_jobs * kMaxEpsTargets * sizeof(EpsState));
+    p->bytes = off;
+    return SNAPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t snaps_eps_sample_workspace(const snaps_eps_job* jobs, int32_t n_jobs) {
+    EpsPlan p;
+    if (plan_eps(jobs, n_jobs, &p) != SNAPS_OK) return 0;
+    return p.bytes;
+}
+
+int snaps_eps_sample(const snaps_eps_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes, void* stream) {
+    EpsPlan p;
+    int rc = plan_eps(jobs, n_jobs, &p);
+    if (rc != SNAPS_OK) return rc;
+    if (!ws) return fail(SNAPS_EINVAL, "workspace is NULL (%zu bytes needed)", p.bytes);
+    if (ws_bytes < p.bytes) return fail(SNAPS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, p.bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    // Jobs grouped by dimensionality (one instantiation per d), in order.
+    std::vector<EpsJob> table;
+    table.reserve(n_jobs);
+    std::vector<int32_t> prefix;
+    struct Group { int d, first, count, blocks, prefix_at; };
+    std::vector<Group> groups;
+    for (int d = 2; d <= kMaxD; ++d) {
+        Group g{d, (int)table.size(), 0, 0, (int)prefix.size()};
+        prefix.push_back(0);
+        for (int i = 0; i < n_jobs; ++i) {
+            if (p.d[i] != d) continue;
+            const snaps_eps_job& j = jobs[i];
+            EpsJob e{};
+            e.cols = j.pop->cols;
+            e.ld = j.pop->ld;
+            e.n = (int32_t)j.pop->n;
+            e.d = d;
+            int f = 0;
+            for (int b = 0; b < 32; ++b)
+                if ((j.mask >> b) & 1u) e.feat[f++] = b;
+            e.sample = j.sample;
+            e.m = j.m;
+            e.n_targets = j.n_targets;
+            for (int t = 0; t < j.n_targets; ++t) e.rank[t] = p.rank[i][t];
+            e.eps = j.eps;
+            const size_t slot = table.size();
+            e.hist = reinterpret_cast<uint32_t*>(base + p.hist) + slot * kMaxEpsTargets * 256;
+            e.state = reinterpret_cast<EpsState*>(base + p.state) + slot * kMaxEpsTargets;
+            table.push_back(e);
+            g.count += 1;
+            g.blocks += j.m;
+            prefix.push_back(g.blocks);
+        }
+        if (g.count == 0) {
+            prefix.pop_back();
+            continue;
+        }
+        groups.push_back(g);
+    }
+    auto& stg = staging();
+    const size_t tb = table.size() * sizeof(EpsJob), pb = prefix.size() * sizeof(int32_t);
+    stg.resize(tb + pb);
+    std::memcpy(stg.data(), table.data(), tb);
+    std::memcpy(stg.data() + tb, prefix.data(), pb);
+    hipError_t e = hipMemcpyAsync(base + p.table, stg.data(), tb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + p.prefix, stg.data() + tb, pb, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "eps table upload");
+    const EpsJob* dt = reinterpret_cast<const EpsJob*>(base + p.table);
+    const int32_t* dp = reinterpret_cast<const int32_t*>(base + p.prefix);
+    for (const Group& g : groups) {
+        e = launch_eps_sample(dt + g.first, dp + g.prefix_at, g.count, g.blocks, g.d, s);
+        if (e != hipSuccess) return hip_fail(e, "eps sampler launch");
     }
     return SNAPS_OK;
 }

@@ -81,6 +81,31 @@ __global__ __launch_bounds__(kSortThreads) void k_rank(RankLaunch L) {
     }
 }
 
+// One 64-object tile of one job per workgroup: ensemble[i] = the mean of
+// the object's four dense ranks (rounded once, from the exact integer sum).
+__global__ __launch_bounds__(64) void k_ensemble(const DevJob* table, int n_jobs, const int32_t* tile_prefix) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_prefix[mid] <= b) lo = mid; else hi = mid;
+    }
+    const DevJob& J = table[lo];
+    if (J.ensemble == nullptr || J.rank == nullptr) return;
+    const int64_t i = (int64_t)(b - tile_prefix[lo]) * kTile + threadIdx.x;
+    if (i >= J.n) return;
+    const int64_t n = J.n;
+    const int64_t sum = (int64_t)J.rank[i] + J.rank[n + i] + J.rank[2 * n + i] + J.rank[3 * n + i];
+    J.ensemble[i] = (float)((double)sum * 0.25);
+}
+
+hipError_t launch_ensemble(const DevJob* table, int n_jobs, const int32_t* tile_prefix, int total_tiles,
+                           hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ensemble, dim3(total_tiles), dim3(64), 0, s, table, n_jobs, tile_prefix);
+    return hipGetLastError();
+}
+
 hipError_t launch_rank(const RankArgs& a, hipStream_t s) {
     RankLaunch L{};
     L.a = a;

@@ -50,6 +50,7 @@ struct DevJob {
     int32_t* indeg;
     float* knn_mean;
     int32_t* rank;           // [4][n] or null
+    float* ensemble;         // [n] mean of the four ranks, or null
     int32_t* knn_ids;        // [n][k] or null
     float* knn_dist;         // [n][k] or null
     float* knn_kth;          // [n] squared float32 distance of the k-th neighbour, or null
@@ -176,6 +177,29 @@ struct AlertArgs {
     int32_t n_jobs;
 };
 
+// Sampled-distance radius selection (one job = one subspace and sample).
+constexpr int kMaxEpsTargets = 8;
+struct EpsState {
+    uint32_t prefix;         // bits of the squared distance found so far
+    uint32_t rem;            // remaining 1-based rank among values with that prefix
+    uint32_t eq;             // values in the last chosen bucket
+    uint32_t next;           // smallest squared-distance bits above the r-th (atomic min)
+    uint32_t need_next;      // the (r + 1)-th is not a tie of the r-th
+    uint32_t bad;            // fewer distances than the rank
+};
+struct EpsJob {
+    const float* cols;
+    int64_t ld;
+    int32_t n, d;
+    int32_t feat[kMaxD];
+    const int32_t* sample;   // [m] object ids
+    int32_t m, n_targets;
+    uint32_t rank[kMaxEpsTargets];   // r = round(target m), 1-based
+    float* eps;              // [n_targets] output
+    uint32_t* hist;          // [n_targets][256] scratch
+    EpsState* state;         // [n_targets] scratch
+};
+
 struct RankArgs {
     const DevJob* table;
     int32_t n_jobs;
@@ -189,6 +213,12 @@ __host__ __device__ constexpr int join_ql(int kc) { return kc < 0 ? 2 : 1; }
 hipError_t launch_index_sort(const IndexArgs& a, int grid, hipStream_t s);
 hipError_t launch_reorder(const Meta& m, int32_t n_jobs, int32_t total_tiles, hipStream_t s);
 hipError_t launch_rank(const RankArgs& a, hipStream_t s);
+hipError_t launch_eps_sample(const EpsJob* jobs, const int32_t* prefix, int n_jobs, int total_blocks, int d,
+                             hipStream_t s);
+// Mean of the four ranks of every object of every job with an ensemble
+// output (after both rank paths); tile_prefix as in Meta.
+hipError_t launch_ensemble(const DevJob* table, int n_jobs, const int32_t* tile_prefix, int total_tiles,
+                           hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t n, int32_t v, hipStream_t s);
 hipError_t launch_serve_finish(const DevJob& j, const LargeIndex& li, float* rk2, float* tmax, uint32_t* tkey,
                                const float* kth, hipStream_t s);

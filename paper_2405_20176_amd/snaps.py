@@ -45,7 +45,8 @@ class c_scores(ctypes.Structure):
 
 class c_job(ctypes.Structure):
     _fields_ = [("pop", ctypes.POINTER(c_population)), ("mask", ctypes.c_uint32), ("k", ctypes.c_int32),
-                ("eps", ctypes.c_float), ("out", c_scores), ("rank", ctypes.c_void_p)]
+                ("eps", ctypes.c_float), ("out", c_scores), ("rank", ctypes.c_void_p),
+                ("ensemble", ctypes.c_void_p)]
 
 
 class c_tuning(ctypes.Structure):
@@ -61,6 +62,15 @@ class c_alert_job(ctypes.Structure):
     _fields_ = [("state", ctypes.c_void_p), ("alerts", ctypes.c_void_p), ("m", ctypes.c_int32),
                 ("pad0", ctypes.c_int32), ("eps_count", ctypes.c_void_p), ("eps_mean", ctypes.c_void_p),
                 ("indeg", ctypes.c_void_p), ("knn_mean", ctypes.c_void_p), ("rank", ctypes.c_void_p)]
+
+
+MAX_EPS_TARGETS = 8
+
+
+class c_eps_job(ctypes.Structure):
+    _fields_ = [("pop", ctypes.POINTER(c_population)), ("mask", ctypes.c_uint32), ("m", ctypes.c_int32),
+                ("sample", ctypes.c_void_p), ("n_targets", ctypes.c_int32),
+                ("target", ctypes.c_float * MAX_EPS_TARGETS), ("eps", ctypes.c_void_p)]
 
 
 _lib = None
@@ -105,6 +115,10 @@ def load_library(path: str = LIB_PATH):
     lib.snaps_serve_state_outputs.argtypes = [vp, i64, i32, i32, P(vp), P(vp), P(vp), P(vp), P(vp)]
     lib.snaps_alerts_score.restype = ctypes.c_int
     lib.snaps_alerts_score.argtypes = [P(c_alert_job), i32, i32, i32, vp]
+    lib.snaps_eps_sample_workspace.restype = sz
+    lib.snaps_eps_sample_workspace.argtypes = [P(c_eps_job), i32]
+    lib.snaps_eps_sample.restype = ctypes.c_int
+    lib.snaps_eps_sample.argtypes = [P(c_eps_job), i32, vp, sz, vp]
     _lib = lib
     return lib
 
@@ -205,15 +219,18 @@ class Job:
     indeg: torch.Tensor
     knn_mean: torch.Tensor
     rank: Optional[torch.Tensor] = None      # [4, n] int32
+    ensemble: Optional[torch.Tensor] = None  # [n] float32, mean of the four ranks
 
     @classmethod
-    def alloc(cls, pop: Population, mask: int, k: int, eps: float, with_rank: bool = True) -> "Job":
+    def alloc(cls, pop: Population, mask: int, k: int, eps: float, with_rank: bool = True,
+              with_ensemble: bool = False) -> "Job":
         dev = pop.cols.device
         n = pop.n
         return cls(pop, int(mask), int(k), float(eps),
                    torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
                    torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
-                   torch.empty((4, n), dtype=torch.int32, device=dev) if with_rank else None)
+                   torch.empty((4, n), dtype=torch.int32, device=dev) if with_rank else None,
+                   torch.empty(n, dtype=torch.float32, device=dev) if (with_rank and with_ensemble) else None)
 
 
 def _c_jobs(jobs: Sequence[Job]):
@@ -226,6 +243,7 @@ def _c_jobs(jobs: Sequence[Job]):
         arr[i].out = c_scores(j.eps_count.data_ptr(), j.eps_mean.data_ptr(), j.indeg.data_ptr(),
                               j.knn_mean.data_ptr())
         arr[i].rank = None if j.rank is None else j.rank.data_ptr()
+        arr[i].ensemble = None if j.ensemble is None else j.ensemble.data_ptr()
     return arr
 
 
@@ -382,3 +400,32 @@ def snaps_alerts_score(jobs: Sequence[AlertJob], stream=None):
             arr[i].knn_mean = j.knn_mean.data_ptr()
             arr[i].rank = None if j.rank is None else j.rank.data_ptr()
         _check(lib.snaps_alerts_score(arr, len(js), d, k, _stream(stream)))
+
+
+def snaps_eps_sample(specs, stream=None):
+    """Sampled-distance radii (Sec. 3.5.3) for several subspaces in one call.
+    ``specs``: sequence of (Population, mask, sample int32 CUDA tensor of
+    object ids, targets); returns one float32 CUDA tensor of radii per spec."""
+    lib = load_library()
+    arr = (c_eps_job * len(specs))()
+    outs = []
+    for i, (pop, mask, sample, targets) in enumerate(specs):
+        if sample.dtype != torch.int32 or not sample.is_contiguous():
+            raise ValueError("sample must be a contiguous int32 tensor of object ids")
+        targets = list(targets)
+        out = torch.empty(len(targets), dtype=torch.float32, device=sample.device)
+        arr[i].pop = ctypes.pointer(pop.c)
+        arr[i].mask = int(mask)
+        arr[i].m = sample.numel()
+        arr[i].sample = sample.data_ptr()
+        arr[i].n_targets = len(targets)
+        for t, v in enumerate(targets):
+            arr[i].target[t] = float(v)
+        arr[i].eps = out.data_ptr()
+        outs.append(out)
+    need = lib.snaps_eps_sample_workspace(arr, len(specs))
+    if need == 0:
+        _check(lib.snaps_eps_sample(arr, len(specs), None, 0, _stream(stream)))
+    ws = _workspace(need, outs[0].device)
+    _check(lib.snaps_eps_sample(arr, len(specs), _ptr(ws), ws.numel(), _stream(stream)))
+    return outs

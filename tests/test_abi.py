@@ -114,6 +114,10 @@ def test_outlier_scores_validation(lib):
         t = c_tuning()
         setattr(t, field, value)
         assert lib.snaps_outlier_scores(ctypes.byref(job), 1, ctypes.byref(t), None, 0, None) == -1, field
+    # an ensemble output needs the rank output
+    ej = c_job.from_buffer_copy(job)
+    ej.ensemble = 0x50
+    assert lib.snaps_outlier_scores(ctypes.byref(ej), 1, None, None, 0, None) == -1
     # the packed LDS index needs no device-wide sort scratch
     tp, tr = c_tuning(), c_tuning()
     tp.index_sort, tr.index_sort = 1, 2
@@ -134,3 +138,29 @@ def test_rank_validation(lib):
     assert lib.snaps_rank(c, c, c, c, 1 << 20, c, None, 0, None) == -1      # needs a workspace
     assert lib.snaps_rank(c, c, c, c, 1 << 20, c, c, 10, None) == -2        # too small
     assert lib.snaps_rank(c, c, c, c, 1 << 31, c, None, 0, None) == -4
+
+
+def test_eps_sampler_validation(lib):
+    from paper_2405_20176_amd.snaps import c_eps_job
+    p = _pop(n=100)
+    j = c_eps_job()
+    j.pop = ctypes.pointer(p)
+    j.mask, j.m, j.sample, j.n_targets, j.eps = 0b111, 10, 0x3000, 2, 0x4000
+    j.target[0], j.target[1] = 1.0, 50.0
+    assert lib.snaps_eps_sample_workspace(ctypes.byref(j), 1) > 0
+    assert lib.snaps_eps_sample(ctypes.byref(j), 0, None, 0, None) == -1             # no jobs
+    assert lib.snaps_eps_sample(ctypes.byref(j), 1, None, 0, None) == -1             # no workspace
+    need = lib.snaps_eps_sample_workspace(ctypes.byref(j), 1)
+    assert lib.snaps_eps_sample(ctypes.byref(j), 1, ctypes.c_void_p(0x1000), need - 1, None) == -2
+    for field, value in (("m", 0), ("m", 101), ("n_targets", 0), ("n_targets", 9), ("sample", None), ("eps", None)):
+        bad = c_eps_job.from_buffer_copy(j)
+        setattr(bad, field, value)
+        assert lib.snaps_eps_sample_workspace(ctypes.byref(bad), 1) == 0, field
+        assert lib.snaps_eps_sample(ctypes.byref(bad), 1, ctypes.c_void_p(0x1000), need, None) == -1, field
+    for t in (0.0, -1.0, float("nan"), 0.04, 99.0):     # r = round(t m) must be in [1, m (n - 1) - 1]
+        bad = c_eps_job.from_buffer_copy(j)
+        bad.target[1] = t
+        assert lib.snaps_eps_sample_workspace(ctypes.byref(bad), 1) == 0, t
+    ok = c_eps_job.from_buffer_copy(j)
+    ok.target[1] = 98.9                                 # r = 989 = m (n - 1) - 1
+    assert lib.snaps_eps_sample_workspace(ctypes.byref(ok), 1) > 0

@@ -185,6 +185,28 @@ def test_index_sorts_agree(S, d):
     check_scores(b, ora, 10, eps, label=f"radix index d={d}")
 
 
+@pytest.mark.parametrize("n", [1000, 40000])
+def test_ensemble_output(S, n):
+    """The ensemble output is the mean of the GPU's own four ranks (exactly),
+    equals the oracle's wherever the four ranks match it, and is written for
+    jobs ranked by either rank path (LDS, or device-wide above 32,768)."""
+    rng = np.random.default_rng(n)
+    x = rng.random((n, 4)).astype(np.float32)
+    pop = S.Population.from_rows(x)
+    jobs = [S.Job.alloc(pop, 0b111, 7, 0.07, with_ensemble=True), S.Job.alloc(pop, 0b1011, 5, 0.09)]
+    S.snaps_outlier_scores(jobs)
+    torch.cuda.synchronize()
+    r = jobs[0].rank.cpu().numpy().astype(np.int64)
+    ens = jobs[0].ensemble.cpu().numpy()
+    np.testing.assert_array_equal(ens, (r.sum(axis=0) / 4.0).astype(np.float32))
+    assert jobs[1].ensemble is None
+    if n <= 1000:
+        ora = run_oracle(x, 0b111, 7, 0.07)
+        same = (r == ora["rank"]).all(axis=0)
+        assert same.mean() > 0.99
+        np.testing.assert_array_equal(ens[same], ora["ensemble"][same].astype(np.float32))
+
+
 def test_determinism(S, c0):
     x, k, eps = c0
     a = run_gpu(S, x, 0b111, k, float(eps))
@@ -511,3 +533,76 @@ def test_graph_plans_replay(S):
     torch.cuda.synchronize()
     for key in ("eps_count", "indeg", "knn_mean"):
         assert torch.equal(getattr(single[0], key), getattr(ref[0], key)), key
+
+
+# ---------------------------------------------------- sampled eps (Sec. 3.5.3)
+
+def _eps_case(S, x, mask, m, targets, seed):
+    rng = np.random.default_rng(seed)
+    n = x.shape[0]
+    sample = np.sort(rng.choice(n, size=m, replace=False)).astype(np.int32)
+    pop = S.Population.from_rows(x)
+    got = S.snaps_eps_sample([(pop, mask, torch.from_numpy(sample).cuda(), targets)])[0].cpu().numpy()
+    P = O.project(x, mask).astype(np.float32)
+    ref = np.array([O.eps_from_sample(P, sample, t) for t in targets], dtype=np.float64)
+    return got, ref
+
+
+@pytest.mark.parametrize("d", [2, 5, 9, 16])
+def test_eps_sampler_against_oracle(S, d):
+    """The GPU radius equals the oracle's for the same sample to float32
+    rounding of the distances, at small, middle and extreme targets
+    (r = 1 and r = m (n - 1) - 1)."""
+    rng = np.random.default_rng(40 + d)
+    n, m = 3000, 64
+    x = rng.random((n, 16)).astype(np.float32)
+    mask = int(sum(1 << f for f in rng.choice(16, size=d, replace=False)))
+    targets = [1.0 / m, 0.5, 10.0, 300.0, 0.0015 * n, 0.15 * n, (m * (n - 1) - 1) / m]
+    got, ref = _eps_case(S, x, mask, m, targets, seed=d)
+    np.testing.assert_allclose(got, ref, rtol=TAU)
+
+
+def test_eps_sampler_ties_and_duplicates(S):
+    """Many exactly equal distances (a coarse lattice with duplicates): the
+    selection handles ties of the r-th and (r+1)-th smallest exactly."""
+    rng = np.random.default_rng(5)
+    x = (rng.integers(0, 4, size=(500, 3)) / 4.0).astype(np.float32)
+    got, ref = _eps_case(S, x, 0b111, 50, [0.02, 1.0, 7.0, 33.3, 120.0, 400.0], seed=1)
+    np.testing.assert_allclose(got, ref, rtol=TAU)
+
+
+def test_eps_sampler_reproduces_the_stored_c1_radii(S, c1):
+    """The stored C1 radii were written by the oracle (m = 128 seeded by the
+    subspace mask, target 10); the GPU sampler with the same samples
+    reproduces them."""
+    x, masks, k, eps_tab = c1
+    pop = S.Population.from_rows(x)
+    n = x.shape[0]
+    specs, want = [], []
+    for i in (0, 104, 560, 5000, 20000, 32751):
+        rng = np.random.default_rng(int(masks[i]))
+        sample = np.sort(rng.choice(n, size=128, replace=False)).astype(np.int32)
+        specs.append((pop, int(masks[i]), torch.from_numpy(sample).cuda(), [10.0]))
+        want.append(eps_tab[i])
+    got = [o.cpu().numpy()[0] for o in S.snaps_eps_sample(specs)]
+    np.testing.assert_allclose(got, want, rtol=TAU)
+
+
+def test_eps_sampler_batched_equals_single(S):
+    rng = np.random.default_rng(8)
+    pops = [S.Population.from_rows(rng.random((n, 15)).astype(np.float32)) for n in (800, 2500)]
+    specs = []
+    for i in range(10):
+        pop = pops[i % 2]
+        d = int(rng.integers(2, 16))
+        mask = int(sum(1 << f for f in rng.choice(15, size=d, replace=False)))
+        sample = torch.from_numpy(np.sort(rng.choice(pop.n, size=40, replace=False)).astype(np.int32)).cuda()
+        specs.append((pop, mask, sample, [0.001 * pop.n, 0.15 * pop.n]))
+    batched = S.snaps_eps_sample(specs)
+    for spec, b in zip(specs, batched):
+        single = S.snaps_eps_sample([spec])[0]
+        assert torch.equal(single, b)
+    # ids outside [0, n) are ignored: too few distances leave the radius NaN
+    bad = torch.full((40,), -1, dtype=torch.int32, device="cuda")
+    out = S.snaps_eps_sample([(pops[0], 0b111, bad, [1.0])])[0]
+    assert torch.isnan(out).all()

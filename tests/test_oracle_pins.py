@@ -64,6 +64,25 @@ def test_tab2_dense_not_competition_ranks():
     assert O.dense_rank(np.array([3, 1, 3, 2])).tolist() == [2, 0, 2, 1]
 
 
+def test_ensemble_of_tab2():
+    """Sec. 5's average over the four methods.  Tab. 2: only point 10 has
+    rank 0 in all four methods, so it alone has ensemble score 0 and is the
+    most outlying by it; every other point has some positive rank.  The
+    score is the mean of the printed ranks whatever the method order, lies
+    between the smallest and largest of them, and equals r when all four
+    are r."""
+    coords, eps, k, table, _ = load_tab2()
+    out = O.outlier_scores(coords, k, eps)
+    ens = out["ensemble"]
+    printed = table[:, [1, 3, 5, 7]].T          # eps_count, eps_mean, indeg, knn_mean ranks
+    assert np.nonzero(ens == 0)[0].tolist() == [9]
+    assert (ens[:9] > 0).all()
+    np.testing.assert_array_equal(ens, O.ensemble(printed[::-1]))
+    assert ((ens >= printed.min(axis=0)) & (ens <= printed.max(axis=0))).all()
+    same = np.full((4, 5), 3)
+    assert (O.ensemble(same) == 3).all()
+
+
 def test_fig3_nested_result_sets():
     coords, eps, k, _, _ = load_tab2()
     q, sets = load_fig3()
