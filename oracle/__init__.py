@@ -25,5 +25,11 @@ from .snaps_oracle import (  # noqa: F401
     selectivity,
     eps_exact_mean_count,
     eps_from_sample,
+    top_n,
+    list_similarity,
+    select_tradeoff,
+    eps_grid,
+    eps_grid_metrics,
+    eps_grid_select,
     eps_sampled_mean_count,
 )

@@ -247,3 +247,73 @@ def eps_sampled_mean_count(X: np.ndarray, target: float, m: int, seed: int) -> n
     rng = np.random.default_rng(seed)
     sample = np.sort(rng.choice(n, size=m, replace=False))
     return eps_from_sample(X, sample, target)
+
+
+# ------------------------------------------------ eps-grid selection (F1) ---
+
+def top_n(ranks: np.ndarray, n: int) -> np.ndarray:
+    """The n most outlying objects of one ranking: the first n ids in
+    (rank, id) order (Sec. 3.5.2 compares the top n = 1 % of |D| of two ranked
+    lists; ties of rank are taken in ascending id)."""
+    ranks = np.asarray(ranks)
+    order = np.lexsort((np.arange(ranks.size), ranks))
+    return order[:n]
+
+
+def list_similarity(top_a: np.ndarray, top_b: np.ndarray, n: int) -> float:
+    """Eq. 2: the fraction of the n objects that are in both top-n lists."""
+    return len(set(np.asarray(top_a).tolist()) & set(np.asarray(top_b).tolist())) / n
+
+
+def select_tradeoff(u_min: np.ndarray, u_max: np.ndarray) -> int:
+    """Eq. 3: the grid index j minimising |U^min_j - U^max_j| (the first one
+    if several tie)."""
+    return int(np.argmin(np.abs(np.asarray(u_min, dtype=np.float64) - np.asarray(u_max, dtype=np.float64))))
+
+
+def eps_grid(eps_min: float, eps_max: float, g: int) -> np.ndarray:
+    """The evenly spaced grid G of Sec. 3.5.2 from eps_min to eps_max, as
+    float32 (the values both sides use)."""
+    j = np.arange(g, dtype=np.float64)
+    return (eps_min + (eps_max - eps_min) * j / (g - 1)).astype(np.float32)
+
+
+def eps_grid_metrics(X: np.ndarray, eps_list) -> tuple[np.ndarray, np.ndarray]:
+    """Neighbour count and mean neighbour distance of every object at every
+    radius of the grid ([g, n] each); the result sets of smaller radii are
+    subsets of the largest one (Sec. 3.5.3, Fig. 4)."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    g = len(eps_list)
+    count = np.zeros((g, n), dtype=np.int64)
+    mean = np.zeros((g, n), dtype=np.float64)
+    for a in range(0, n, 512):
+        D = pair_distances(X[a:a + 512], X)
+        D[np.arange(D.shape[0]), np.arange(a, a + D.shape[0])] = np.inf
+        for j, e in enumerate(eps_list):
+            hit = D <= float(e)
+            c = hit.sum(axis=1)
+            s = np.where(hit, D, 0.0).sum(axis=1)
+            count[j, a:a + D.shape[0]] = c
+            mean[j, a:a + D.shape[0]] = np.where(c > 0, s / np.maximum(c, 1), 0.0)
+    return count, mean
+
+
+def eps_grid_select(count: np.ndarray, mean: np.ndarray, n_top: int) -> dict:
+    """Sec. 3.5.2 on given per-radius metrics: for both DSSJ metrics (number
+    of neighbours, mean neighbour distance) the ranking at every radius, the
+    similarity of its top n to those of the smallest and largest radius
+    (U^min, U^max, Eq. 2) and the selected grid index (Eq. 3)."""
+    g = count.shape[0]
+    u = np.zeros((2, 2, g))
+    sel = np.zeros(2, dtype=np.int64)
+    for metric in range(2):
+        tops = []
+        for j in range(g):
+            keys = rank_keys(count[j], mean[j], count[j], mean[j])
+            tops.append(top_n(dense_rank(keys[metric]), n_top))
+        for j in range(g):
+            u[metric, 0, j] = list_similarity(tops[0], tops[j], n_top)
+            u[metric, 1, j] = list_similarity(tops[g - 1], tops[j], n_top)
+        sel[metric] = select_tradeoff(u[metric, 0], u[metric, 1])
+    return dict(similarity=u, select=sel)

@@ -53,3 +53,23 @@ def exact_fp32_variant(coords, scale=100.0, shift=64.0, denom=512.0):
     exact tie of point 1's third neighbour is then resolved only by id)."""
     ints = np.round(scale * np.asarray(coords, dtype=np.float64))
     return ((ints + shift) / denom).astype(np.float32)
+
+
+def load_eps_select_example():
+    """Sec. 3.5.2 example: n, the three top-n sets, and the printed U^min and
+    U^max."""
+    sets, n, umin, umax = [], 0, None, None
+    with open(os.path.join(HERE, "eps_select_example.txt")) as fh:
+        for line in fh:
+            t = line.split()
+            if not t or t[0].startswith("#"):
+                continue
+            if t[0] == "N":
+                n = int(t[1])
+            elif t[0] == "S":
+                sets.append([int(v) for v in t[2:]])
+            elif t[0] == "UMIN":
+                umin = [float(v) for v in t[1:]]
+            elif t[0] == "UMAX":
+                umax = [float(v) for v in t[1:]]
+    return n, sets, umin, umax

@@ -398,3 +398,45 @@ def test_c_twin_query_subset_mode():
     sub = C.join(x, 7, 0.2, band=(0.19, 0.21), qids=q)
     for key in ("knn_ids", "knn_dist", "knn_next", "eps_count", "eps_sum", "band"):
         np.testing.assert_array_equal(sub[key], full[key][q])
+
+
+# ------------------------------------------------ eps-grid selection ---
+
+def test_eps_selection_worked_example():
+    """Sec. 3.5.2's example: Eq. 2 on the three printed top-10 sets gives the
+    printed U^min = {1.0, 0.4, 0.2} and U^max = {0.2, 0.5, 1.0}; Eq. 3 then
+    selects the middle radius (|0.4 - 0.5| is the smallest gap); a list
+    compared with itself matches fully."""
+    from tests.golden import load_eps_select_example
+    n, sets, umin, umax = load_eps_select_example()
+    got_min = [O.list_similarity(sets[0], s, n) for s in sets]
+    got_max = [O.list_similarity(sets[-1], s, n) for s in sets]
+    assert got_min == umin and got_max == umax
+    assert O.select_tradeoff(got_min, got_max) == 1
+    assert O.select_tradeoff([1.0, 0.6, 0.5, 0.2], [0.2, 0.5, 0.6, 1.0]) == 1   # first of two equal gaps
+
+
+def test_top_n_takes_ties_in_id_order():
+    ranks = np.array([2, 0, 1, 0, 1, 3])
+    assert O.top_n(ranks, 3).tolist() == [1, 3, 2]
+    assert O.top_n(ranks, 6).tolist() == [1, 3, 2, 4, 0, 5]
+
+
+def test_eps_grid_metrics_nested_and_equal_to_the_join():
+    """The grid's result sets are nested (counts and sums grow with the
+    radius, Sec. 3.5.3) and each equals the plain eps-join at that radius."""
+    rng = np.random.default_rng(21)
+    x = rng.random((300, 3))
+    grid = O.eps_grid(0.05, 0.3, 6)
+    count, mean = O.eps_grid_metrics(x, grid)
+    assert (np.diff(count, axis=0) >= 0).all()
+    sums = count * mean
+    assert (np.diff(sums, axis=0) >= -1e-12).all()
+    for j, e in enumerate(grid):
+        c, m = O.eps_join(x, float(e))
+        np.testing.assert_array_equal(count[j], c)
+        np.testing.assert_allclose(mean[j], m, rtol=1e-12)
+    np.testing.assert_allclose(grid, [0.05, 0.1, 0.15, 0.2, 0.25, 0.3], rtol=1e-7)
+    sel = O.eps_grid_select(count, mean, 3)
+    assert sel["similarity"].shape == (2, 2, 6)
+    assert (sel["similarity"][:, 0, 0] == 1.0).all() and (sel["similarity"][:, 1, -1] == 1.0).all()
