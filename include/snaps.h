@@ -307,6 +307,37 @@ size_t snaps_eps_sample_workspace(const snaps_eps_job* jobs, int32_t n_jobs);
  * memory, read during the call.  Asynchronous on stream. */
 int snaps_eps_sample(const snaps_eps_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Radius between under- and overfitting (paper Sec. 3.5.2, Eq. 2-3).  For an
+ * ascending grid of radii eps_1 .. eps_g (the paper spaces them evenly from
+ * eps_min to eps_max, which snaps_eps_sample finds): the neighbour count and
+ * mean neighbour distance of every object at every radius (one range join at
+ * eps_g; the result sets of smaller radii are subsets of it, Sec. 3.5.3), the
+ * rankings of both metrics at every radius, the similarity (Eq. 2) of each
+ * ranking's top n (in rank, then id order) to those of eps_1 (U^min) and eps_g
+ * (U^max), and the index of the radius minimising |U^min - U^max| (Eq. 3, the
+ * first of equal gaps).  Metric 0 is the number of neighbours, metric 1 the
+ * mean neighbour distance (Sec. 3.5.1). */
+#define SNAPS_MAX_GRID 16
+typedef struct {
+    const snaps_population* pop;   /* columns 16-byte aligned and ld a multiple of 4: this pass
+                                      reads whole 4-object groups, up to index ld - 1 of a column */
+    uint32_t mask;                 /* subspace */
+    int32_t n_grid;                /* 2..SNAPS_MAX_GRID */
+    float eps[SNAPS_MAX_GRID];     /* strictly ascending radii, > 0 and finite */
+    int32_t top_n;                 /* n of Eq. 2, 1..n (the paper: 1 % of the population) */
+    int32_t* count;                /* [n_grid][n] device or NULL: neighbours per object and radius */
+    float* mean;                   /* [n_grid][n] device or NULL: mean neighbour distance (0 if none) */
+    float* similarity;             /* [2][2][n_grid] device: per metric, U^min then U^max */
+    int32_t* select;               /* [2] device: selected grid index per metric */
+} snaps_eps_grid_job;
+
+/* Workspace bytes of snaps_eps_grid for these jobs (0 if a job is invalid). */
+size_t snaps_eps_grid_workspace(const snaps_eps_grid_job* jobs, int32_t n_jobs);
+/* Selection for every job (any mix of populations and subspaces).  The job
+ * list is host memory, read during the call.  Asynchronous on stream. */
+int snaps_eps_grid(const snaps_eps_grid_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

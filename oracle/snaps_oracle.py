@@ -312,8 +312,12 @@ def eps_grid_select(count: np.ndarray, mean: np.ndarray, n_top: int) -> dict:
         for j in range(g):
             keys = rank_keys(count[j], mean[j], count[j], mean[j])
             tops.append(top_n(dense_rank(keys[metric]), n_top))
+        both = np.zeros((2, g), dtype=np.int64)          # |top_1 & top_j|, |top_g & top_j|
         for j in range(g):
+            both[0, j] = len(set(tops[0].tolist()) & set(tops[j].tolist()))
+            both[1, j] = len(set(tops[g - 1].tolist()) & set(tops[j].tolist()))
             u[metric, 0, j] = list_similarity(tops[0], tops[j], n_top)
             u[metric, 1, j] = list_similarity(tops[g - 1], tops[j], n_top)
-        sel[metric] = select_tradeoff(u[metric, 0], u[metric, 1])
+        # the same n divides both, so the exact gaps compare as integers
+        sel[metric] = select_tradeoff(both[0], both[1])
     return dict(similarity=u, select=sel)

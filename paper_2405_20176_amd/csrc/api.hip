@@ -1188,3 +1188,133 @@ int snaps_eps_sample(const snaps_eps_job* jobs, int32_t n_jobs, void* ws, size_t
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ eps grid
+
+namespace {
+
+struct GridPlan {
+    std::vector<int> d, words;
+    size_t table = 0, prefix = 0, scratch = 0, bytes = 0;
+    std::vector<size_t> count_off, mean_off, member_off;
+};
+
+int plan_grid(const snaps_eps_grid_job* jobs, int32_t n_jobs, GridPlan* p) {
+    if (n_jobs < 1 || !jobs) return fail(SNAPS_EINVAL, "need at least one eps-grid job");
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += align_up(b);
+        return o;
+    };
+    p->table = take((size_t)n_jobs * sizeof(GridJob));
+    p->prefix = take((size_t)(n_jobs + kMaxD + 2) * sizeof(int32_t));
+    int64_t tiles = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const snaps_eps_grid_job& j = jobs[i];
+        int rc = check_population(j.pop, j.mask);
+        if (rc != SNAPS_OK) return fail(rc, "eps-grid job %d: %s", i, g_error.c_str());
+        const int64_t n = j.pop->n;
+        if ((reinterpret_cast<uintptr_t>(j.pop->cols) & 15u) != 0 || (j.pop->ld & 3) != 0)
+            return fail(SNAPS_EINVAL, "eps-grid job %d: columns must be 16-byte aligned with ld a multiple of 4", i);
+        if (j.n_grid < 2 || j.n_grid > kMaxGrid)
+            return fail(SNAPS_EINVAL, "eps-grid job %d: n_grid must be in [2, %d]", i, kMaxGrid);
+        for (int g = 0; g < j.n_grid; ++g) {
+            if (!(j.eps[g] > 0.f) || !std::isfinite(j.eps[g]) || (g > 0 && !(j.eps[g] > j.eps[g - 1])))
+                return fail(SNAPS_EINVAL, "eps-grid job %d: radii must be positive, finite and strictly ascending", i);
+        }
+        if (j.top_n < 1 || j.top_n > n) return fail(SNAPS_EINVAL, "eps-grid job %d: top_n must be in [1, n]", i);
+        if (!j.similarity || !j.select) return fail(SNAPS_EINVAL, "eps-grid job %d: similarity and select are required", i);
+        p->d.push_back(popcount32(j.mask));
+        const int words = (int)((n + 31) / 32);
+        p->words.push_back(words);
+        p->count_off.push_back(j.count ? 0 : take((size_t)j.n_grid * n * sizeof(int32_t)));
+        p->mean_off.push_back(j.mean ? 0 : take((size_t)j.n_grid * n * sizeof(float)));
+        p->member_off.push_back(take((size_t)2 * j.n_grid * words * sizeof(uint32_t)));
+        tiles += (n + kTile - 1) / kTile;
+    }
+    if (tiles > INT32_MAX) return fail(SNAPS_EUNSUPPORTED, "too many query tiles in one call");
+    p->bytes = off;
+    return SNAPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t snaps_eps_grid_workspace(const snaps_eps_grid_job* jobs, int32_t n_jobs) {
+    GridPlan p;
+    if (plan_grid(jobs, n_jobs, &p) != SNAPS_OK) return 0;
+    return p.bytes;
+}
+
+int snaps_eps_grid(const snaps_eps_grid_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes, void* stream) {
+    GridPlan p;
+    int rc = plan_grid(jobs, n_jobs, &p);
+    if (rc != SNAPS_OK) return rc;
+    if (!ws) return fail(SNAPS_EINVAL, "workspace is NULL (%zu bytes needed)", p.bytes);
+    if (ws_bytes < p.bytes) return fail(SNAPS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, p.bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    std::vector<GridJob> table;
+    table.reserve(n_jobs);
+    std::vector<int32_t> prefix;
+    struct Group { int d, first, count, tiles, prefix_at; };
+    std::vector<Group> groups;
+    for (int d = 2; d <= kMaxD; ++d) {
+        Group g{d, (int)table.size(), 0, 0, (int)prefix.size()};
+        prefix.push_back(0);
+        for (int i = 0; i < n_jobs; ++i) {
+            if (p.d[i] != d) continue;
+            const snaps_eps_grid_job& j = jobs[i];
+            GridJob e{};
+            e.cols = j.pop->cols;
+            e.ld = j.pop->ld;
+            e.n = (int32_t)j.pop->n;
+            e.d = d;
+            int f = 0;
+            for (int b = 0; b < 32; ++b)
+                if ((j.mask >> b) & 1u) e.feat[f++] = b;
+            e.g = j.n_grid;
+            e.top_n = j.top_n;
+            for (int r = 0; r < kMaxGrid; ++r) {
+                const float er = j.eps[r < j.n_grid ? r : j.n_grid - 1];
+                e.e2[r] = (float)((double)er * (double)er);
+            }
+            e.count = j.count ? j.count : reinterpret_cast<int32_t*>(base + p.count_off[i]);
+            e.mean = j.mean ? j.mean : reinterpret_cast<float*>(base + p.mean_off[i]);
+            e.member = reinterpret_cast<uint32_t*>(base + p.member_off[i]);
+            e.words = p.words[i];
+            e.similarity = j.similarity;
+            e.select = j.select;
+            table.push_back(e);
+            g.count += 1;
+            g.tiles += (int)((j.pop->n + kTile - 1) / kTile);
+            prefix.push_back(g.tiles);
+        }
+        if (g.count == 0) {
+            prefix.pop_back();
+            continue;
+        }
+        groups.push_back(g);
+    }
+    auto& stg = staging();
+    const size_t tb = table.size() * sizeof(GridJob), pb = prefix.size() * sizeof(int32_t);
+    stg.resize(tb + pb);
+    std::memcpy(stg.data(), table.data(), tb);
+    std::memcpy(stg.data() + tb, prefix.data(), pb);
+    hipError_t e = hipMemcpyAsync(base + p.table, stg.data(), tb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + p.prefix, stg.data() + tb, pb, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "eps-grid table upload");
+    const GridJob* dt = reinterpret_cast<const GridJob*>(base + p.table);
+    const int32_t* dp = reinterpret_cast<const int32_t*>(base + p.prefix);
+    for (const Group& g : groups) {
+        e = launch_grid_join(dt + g.first, dp + g.prefix_at, g.count, g.tiles, g.d, s);
+        if (e != hipSuccess) return hip_fail(e, "eps-grid join launch");
+    }
+    e = launch_grid_select(dt, n_jobs, s);
+    if (e != hipSuccess) return hip_fail(e, "eps-grid selection launch");
+    return SNAPS_OK;
+}
+
+}  // extern "C"

@@ -200,6 +200,25 @@ struct EpsJob {
     EpsState* state;         // [n_targets] scratch
 };
 
+// Radius selection on a grid of radii (one job = one subspace and grid).
+constexpr int kMaxGrid = 16;
+struct GridJob {
+    const float* cols;       // 16-byte aligned columns, ld a multiple of 4
+    int64_t ld;
+    int32_t n, d;
+    int32_t feat[kMaxD];
+    int32_t g;               // radii in the grid
+    int32_t top_n;           // n of Eq. 2
+    float e2[kMaxGrid];      // squared radii as the joins compare them (float32 of the exact square)
+    int32_t* count;          // [g][n] neighbours per object and radius
+    float* mean;             // [g][n] mean neighbour distance
+    uint32_t* member;        // [2][g][words] top-n bit sets (scratch)
+    int32_t words;           // ceil(n / 32)
+    int32_t pad0;
+    float* similarity;       // [2][2][g] U^min, U^max per metric
+    int32_t* select;         // [2] selected radius index per metric
+};
+
 struct RankArgs {
     const DevJob* table;
     int32_t n_jobs;
@@ -213,6 +232,9 @@ __host__ __device__ constexpr int join_ql(int kc) { return kc < 0 ? 2 : 1; }
 hipError_t launch_index_sort(const IndexArgs& a, int grid, hipStream_t s);
 hipError_t launch_reorder(const Meta& m, int32_t n_jobs, int32_t total_tiles, hipStream_t s);
 hipError_t launch_rank(const RankArgs& a, hipStream_t s);
+hipError_t launch_grid_join(const GridJob* jobs, const int32_t* tile_prefix, int n_jobs, int total_tiles, int d,
+                            hipStream_t s);
+hipError_t launch_grid_select(const GridJob* jobs, int n_jobs, hipStream_t s);
 hipError_t launch_eps_sample(const EpsJob* jobs, const int32_t* prefix, int n_jobs, int total_blocks, int d,
                              hipStream_t s);
 // Mean of the four ranks of every object of every job with an ensemble

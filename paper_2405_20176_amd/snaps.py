@@ -73,6 +73,15 @@ class c_eps_job(ctypes.Structure):
                 ("target", ctypes.c_float * MAX_EPS_TARGETS), ("eps", ctypes.c_void_p)]
 
 
+MAX_GRID = 16
+
+
+class c_eps_grid_job(ctypes.Structure):
+    _fields_ = [("pop", ctypes.POINTER(c_population)), ("mask", ctypes.c_uint32), ("n_grid", ctypes.c_int32),
+                ("eps", ctypes.c_float * MAX_GRID), ("top_n", ctypes.c_int32), ("count", ctypes.c_void_p),
+                ("mean", ctypes.c_void_p), ("similarity", ctypes.c_void_p), ("select", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -119,6 +128,10 @@ def load_library(path: str = LIB_PATH):
     lib.snaps_eps_sample_workspace.argtypes = [P(c_eps_job), i32]
     lib.snaps_eps_sample.restype = ctypes.c_int
     lib.snaps_eps_sample.argtypes = [P(c_eps_job), i32, vp, sz, vp]
+    lib.snaps_eps_grid_workspace.restype = sz
+    lib.snaps_eps_grid_workspace.argtypes = [P(c_eps_grid_job), i32]
+    lib.snaps_eps_grid.restype = ctypes.c_int
+    lib.snaps_eps_grid.argtypes = [P(c_eps_grid_job), i32, vp, sz, vp]
     _lib = lib
     return lib
 
@@ -428,4 +441,41 @@ def snaps_eps_sample(specs, stream=None):
         _check(lib.snaps_eps_sample(arr, len(specs), None, 0, _stream(stream)))
     ws = _workspace(need, outs[0].device)
     _check(lib.snaps_eps_sample(arr, len(specs), _ptr(ws), ws.numel(), _stream(stream)))
+    return outs
+
+
+def snaps_eps_grid(specs, with_metrics: bool = False, stream=None):
+    """Radius selection on grids of radii (Sec. 3.5.2).  ``specs``: sequence
+    of (Population, mask, radii, top_n).  Returns per spec a dict with
+    ``similarity`` [2, 2, g] (metric: count, mean; U^min, U^max), ``select``
+    [2] and, with ``with_metrics``, ``count`` / ``mean`` [g, n] (CUDA
+    tensors)."""
+    lib = load_library()
+    arr = (c_eps_grid_job * len(specs))()
+    outs = []
+    for i, (pop, mask, radii, top_n) in enumerate(specs):
+        radii = [float(r) for r in radii]
+        g = len(radii)
+        dev = pop.cols.device
+        o = {"similarity": torch.empty((2, 2, g), dtype=torch.float32, device=dev),
+             "select": torch.empty(2, dtype=torch.int32, device=dev)}
+        if with_metrics:
+            o["count"] = torch.empty((g, pop.n), dtype=torch.int32, device=dev)
+            o["mean"] = torch.empty((g, pop.n), dtype=torch.float32, device=dev)
+        arr[i].pop = ctypes.pointer(pop.c)
+        arr[i].mask = int(mask)
+        arr[i].n_grid = g
+        for r, v in enumerate(radii):
+            arr[i].eps[r] = v
+        arr[i].top_n = int(top_n)
+        arr[i].count = o["count"].data_ptr() if with_metrics else None
+        arr[i].mean = o["mean"].data_ptr() if with_metrics else None
+        arr[i].similarity = o["similarity"].data_ptr()
+        arr[i].select = o["select"].data_ptr()
+        outs.append(o)
+    need = lib.snaps_eps_grid_workspace(arr, len(specs))
+    if need == 0:
+        _check(lib.snaps_eps_grid(arr, len(specs), None, 0, _stream(stream)))
+    ws = _workspace(need, outs[0]["select"].device)
+    _check(lib.snaps_eps_grid(arr, len(specs), _ptr(ws), ws.numel(), _stream(stream)))
     return outs

@@ -606,3 +606,64 @@ def test_eps_sampler_batched_equals_single(S):
     bad = torch.full((40,), -1, dtype=torch.int32, device="cuda")
     out = S.snaps_eps_sample([(pops[0], 0b111, bad, [1.0])])[0]
     assert torch.isnan(out).all()
+
+
+# ------------------------------------------- eps-grid selection (Sec. 3.5.2)
+
+def _grid_exempt(P, radii):
+    """Per radius, objects with a float64 distance within tau of it."""
+    D = O.pair_distances(P, P)
+    np.fill_diagonal(D, np.inf)
+    return np.stack([(np.abs(D - float(r)) <= TAU * float(r)).any(axis=1) for r in radii])
+
+
+@pytest.mark.parametrize("d", [2, 5, 9])
+def test_eps_grid_against_oracle(S, d):
+    """Per-object counts and means at every radius meet the oracle; the
+    similarity curves and the selected radii are exactly the oracle's
+    selection applied to the GPU's own per-radius metrics, and equal the
+    oracle's outright when no object sits on a radius."""
+    rng = np.random.default_rng(60 + d)
+    n = 1500
+    x = rng.random((n, 16)).astype(np.float32)
+    mask = int(sum(1 << f for f in rng.choice(16, size=d, replace=False)))
+    P = O.project(x, mask).astype(np.float32)
+    sample = np.sort(rng.choice(n, size=64, replace=False))
+    lo, hi = O.eps_from_sample(P, sample, 2.0), O.eps_from_sample(P, sample, 0.15 * n)
+    radii = O.eps_grid(float(lo), float(hi), 8)
+    top = 15
+    pop = S.Population.from_rows(x)
+    out = S.snaps_eps_grid([(pop, mask, radii, top)], with_metrics=True)[0]
+    cnt = out["count"].cpu().numpy()
+    mean = out["mean"].cpu().numpy()
+    rc, rm = O.eps_grid_metrics(P, radii)
+    ex = _grid_exempt(P, radii)
+    assert ((cnt == rc) | ex).all()
+    rel = np.abs(mean - rm) / np.maximum(rm, 1e-30)
+    assert ((rel <= TAU) | ex | ((rm == 0) & (mean == 0))).all()
+    mine = O.eps_grid_select(cnt, mean.astype(np.float64), top)
+    np.testing.assert_array_equal(out["similarity"].cpu().numpy(), mine["similarity"].astype(np.float32))
+    np.testing.assert_array_equal(out["select"].cpu().numpy(), mine["select"])
+    if not ex.any():
+        ref = O.eps_grid_select(rc, rm, top)
+        np.testing.assert_array_equal(out["select"].cpu().numpy()[0], ref["select"][0])
+
+
+def test_eps_grid_batched_equals_single_and_degenerate_top(S):
+    rng = np.random.default_rng(9)
+    pops = [S.Population.from_rows(rng.random((n, 15)).astype(np.float32)) for n in (700, 1300)]
+    specs = []
+    for i in range(8):
+        pop = pops[i % 2]
+        d = int(rng.integers(2, 16))
+        mask = int(sum(1 << f for f in rng.choice(15, size=d, replace=False)))
+        r0 = 0.05 * math.sqrt(d)
+        specs.append((pop, mask, [r0 * (1 + 0.5 * j) for j in range(6)], max(1, pop.n // 100)))
+    batched = S.snaps_eps_grid(specs)
+    for spec, b in zip(specs, batched):
+        single = S.snaps_eps_grid([spec])[0]
+        for key in ("similarity", "select"):
+            assert torch.equal(single[key], b[key]), key
+    # top n = every object: every list is the whole population, all gaps are 0
+    allt = S.snaps_eps_grid([(pops[0], 0b111, [0.05, 0.1, 0.2], pops[0].n)])[0]
+    assert (allt["similarity"] == 1).all() and (allt["select"] == 0).all()
