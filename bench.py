@@ -207,6 +207,44 @@ def eps_sampler_bench(S, pop, masks, n, dev, m: int = 128):
             "note": "includes the host-to-device upload of the job table"}
 
 
+def eps_grid_bench(S, pop, masks, n, dev, spaces: int = 1024, g: int = 16, m: int = 128):
+    """The paper's eps selection (Sec. 3.5.2-3.5.3) on an evenly spaced slice
+    of the subspaces: eps_min / eps_max from the sampler (selectivity 0.1 %
+    and 15 %), a grid of g evenly spaced radii, the per-radius rankings and
+    the Eq. 3 choice for both DSSJ metrics, top n = 1 % of the population."""
+    import torch
+    idx = np.linspace(0, len(masks) - 1, min(spaces, len(masks))).astype(int)
+    rng = np.random.default_rng(3576)
+    specs = []
+    for i in idx:
+        sample = np.sort(rng.choice(n, size=m, replace=False)).astype(np.int32)
+        specs.append((pop, int(masks[i]), torch.from_numpy(sample).to(dev), [0.001 * n, 0.15 * n]))
+    top = max(1, int(round(0.01 * n)))
+
+    def run():
+        radii = torch.stack(S.snaps_eps_sample(specs)).cpu().numpy()
+        grid = [(pop, int(masks[i]), np.linspace(lo, hi, g).astype(np.float32), top)
+                for i, (lo, hi) in zip(idx, radii)]
+        return S.snaps_eps_grid(grid), radii
+
+    run()                                           # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs, radii = run()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    sel = torch.stack([o["select"] for o in outs]).cpu().numpy()
+    # the slice is evenly spaced over subspaces ordered by (d, mask), so its
+    # mix of dimensionalities follows the full list
+    full = sec * len(masks) / len(idx)
+    log(f"eps-grid selection: {len(idx)} subspaces in {sec:.2f} s")
+    return {"seconds": sec, "subspaces": len(idx), "grid": g, "top_n": top, "sample_size": m,
+            "seconds_per_subspace": sec / len(idx), "extrapolated_all_subspaces_s": full,
+            "pairs_per_subspace": float(n) * (n - 1),
+            "selected_index_median": [float(np.median(sel[:, 0])), float(np.median(sel[:, 1]))],
+            "clock": "host wall clock around sampler + grid calls (includes table uploads and the radii copy)"}
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -246,6 +284,8 @@ def main():
     ap.add_argument("--eager", action="store_true", help="launch the batched passes directly, without HIP graphs")
     ap.add_argument("--no-eps-sampler", dest="eps_sampler", action="store_false",
                     help="skip timing the sampled eps_min / eps_max radii of every subspace")
+    ap.add_argument("--no-eps-grid", dest="eps_grid", action="store_false",
+                    help="skip timing the eps-grid selection on a slice of the subspaces")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain MIB-MiB device copy (counter calibration) and exit")
     a = ap.parse_args()
@@ -421,6 +461,8 @@ def main():
 
     if a.eps_sampler:
         result["eps_sampler"] = eps_sampler_bench(S, pop, masks, n, dev)
+    if a.eps_grid:
+        result["eps_grid_selection"] = eps_grid_bench(S, pop, masks, n, dev)
 
     if a.serve_seconds > 0:
         del plans

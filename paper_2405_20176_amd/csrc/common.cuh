@@ -36,6 +36,23 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// h[bin] += 1 for every lane of the wavefront with active set, with one LDS
+// atomic per distinct bin (lanes of one bin are counted by a ballot): keys
+// that crowd into few bins (small integer counts) would otherwise serialise
+// on one address.  Must be called by every lane of the wavefront.
+__device__ __forceinline__ void wave_hist_add(unsigned* h, uint32_t bin, bool active) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long pending = __ballot(active);
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)bin, leader);
+        const bool mine = ((pending >> lane) & 1ull) != 0ull;
+        const unsigned long long same = __ballot(mine && bin == b);
+        if (lane == leader) atomicAdd(&h[b], (unsigned)__popcll(same));
+        pending &= ~same;
+    }
+}
+
 // Inclusive scan over a 64-lane wavefront.
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
     const int lane = threadIdx.x & 63;

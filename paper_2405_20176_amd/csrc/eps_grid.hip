@@ -55,6 +55,9 @@ __global__ __launch_bounds__(64) void k_grid_join(const GridJob* jobs, const int
     float q[D];
 #pragma unroll
     for (int f = 0; f < D; ++f) q[f] = J.cols[(int64_t)J.feat[f] * J.ld + qi];
+    float e2[kMaxGrid];                                   // uniform: held in scalar registers
+#pragma unroll
+    for (int r = 0; r < kMaxGrid; ++r) e2[r] = J.e2[r];
     const float emax2 = J.e2[g - 1];
     typedef float f4 __attribute__((ext_vector_type(4)));
     for (int c0 = 0; c0 < n; c0 += 4) {
@@ -71,8 +74,9 @@ __global__ __launch_bounds__(64) void k_grid_join(const GridJob* jobs, const int
                 dd = fmaf(tq, tq, dd);
             }
             if (dd <= emax2 && c < n && c != qi && valid) {
-                int j = 0;
-                while (dd > J.e2[j]) ++j;                  // the smallest radius that holds it
+                int j = 0;                                 // the smallest radius that holds it
+#pragma unroll
+                for (int r = 0; r < kMaxGrid - 1; ++r) j += (r < g - 1 && dd > e2[r]) ? 1 : 0;
                 cnt[j][lane] += 1u;
                 sm[j][lane] += (double)__builtin_amdgcn_sqrtf(dd);   // hardware sqrt, <= 1 ulp
             }
@@ -117,10 +121,15 @@ __global__ __launch_bounds__(kTopThreads) void k_grid_top(const GridJob* jobs) {
         for (int x = tid; x < 256; x += blockDim.x) hist[x] = 0u;
         __syncthreads();
         const unsigned pre = s_prefix;
-        for (int64_t i = tid; i < n; i += blockDim.x) {
-            const uint32_t k = grid_key(J, metric, j, i);
-            if (pass > 0 && (k >> (shift + 8)) != pre) continue;
-            atomicAdd(&hist[(k >> shift) & 255u], 1u);
+        for (int64_t base = 0; base < n; base += blockDim.x) {     // same trip count in every lane
+            const int64_t i = base + tid;
+            uint32_t k = 0u;
+            bool on = i < n;
+            if (on) {
+                k = grid_key(J, metric, j, i);
+                on = pass == 0 || (k >> (shift + 8)) == pre;
+            }
+            wave_hist_add(hist, (k >> shift) & 255u, on);
         }
         __syncthreads();
         if (tid == 0) {
