@@ -31,5 +31,7 @@ from .snaps_oracle import (  # noqa: F401
     eps_grid,
     eps_grid_metrics,
     eps_grid_select,
+    k_grid_metrics,
+    k_grid_select,
     eps_sampled_mean_count,
 )

@@ -299,20 +299,17 @@ def eps_grid_metrics(X: np.ndarray, eps_list) -> tuple[np.ndarray, np.ndarray]:
     return count, mean
 
 
-def eps_grid_select(count: np.ndarray, mean: np.ndarray, n_top: int) -> dict:
-    """Sec. 3.5.2 on given per-radius metrics: for both DSSJ metrics (number
-    of neighbours, mean neighbour distance) the ranking at every radius, the
-    similarity of its top n to those of the smallest and largest radius
-    (U^min, U^max, Eq. 2) and the selected grid index (Eq. 3)."""
-    g = count.shape[0]
+def _grid_select(keys_at, g: int, n_top: int) -> dict:
+    """Sec. 3.5.2 / 3.6.2 given the ranking keys of both metrics at every
+    grid point (keys_at(j) -> (key of metric 0, key of metric 1)): top n per
+    ranking, Eq. 2 similarities to the first (U^min) and last (U^max) grid
+    point, and Eq. 3 on the exact intersection counts."""
     u = np.zeros((2, 2, g))
     sel = np.zeros(2, dtype=np.int64)
+    keys = [keys_at(j) for j in range(g)]
     for metric in range(2):
-        tops = []
-        for j in range(g):
-            keys = rank_keys(count[j], mean[j], count[j], mean[j])
-            tops.append(top_n(dense_rank(keys[metric]), n_top))
-        both = np.zeros((2, g), dtype=np.int64)          # |top_1 & top_j|, |top_g & top_j|
+        tops = [top_n(dense_rank(keys[j][metric]), n_top) for j in range(g)]
+        both = np.zeros((2, g), dtype=np.int64)
         for j in range(g):
             both[0, j] = len(set(tops[0].tolist()) & set(tops[j].tolist()))
             both[1, j] = len(set(tops[g - 1].tolist()) & set(tops[j].tolist()))
@@ -321,3 +318,35 @@ def eps_grid_select(count: np.ndarray, mean: np.ndarray, n_top: int) -> dict:
         # the same n divides both, so the exact gaps compare as integers
         sel[metric] = select_tradeoff(both[0], both[1])
     return dict(similarity=u, select=sel)
+
+
+def k_grid_metrics(X: np.ndarray, ks) -> tuple[np.ndarray, np.ndarray]:
+    """In-degree and mean kNN distance of every object for every k of the
+    grid ([g, n] each), from the k_max lists, which hold those of every
+    smaller k (Sec. 3.6.2)."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    kmax = int(max(ks))
+    ids, dist = knn(X, kmax)
+    deg = np.zeros((len(ks), n), dtype=np.int64)
+    kmean = np.zeros((len(ks), n), dtype=np.float64)
+    for j, k in enumerate(ks):
+        deg[j] = indegree(ids[:, :k], n)
+        kmean[j] = dist[:, :k].sum(axis=1) / k
+    return deg, kmean
+
+
+def k_grid_select(indeg: np.ndarray, kmean: np.ndarray, n_top: int) -> dict:
+    """Sec. 3.6.2 on given per-k metrics: metric 0 is the in-degree
+    (ascending), metric 1 the mean kNN distance (descending)."""
+    g = indeg.shape[0]
+    return _grid_select(lambda j: rank_keys(indeg[j], kmean[j], indeg[j], kmean[j])[2:], g, n_top)
+
+
+def eps_grid_select(count: np.ndarray, mean: np.ndarray, n_top: int) -> dict:
+    """Sec. 3.5.2 on given per-radius metrics: for both DSSJ metrics (number
+    of neighbours, mean neighbour distance) the ranking at every radius, the
+    similarity of its top n to those of the smallest and largest radius
+    (U^min, U^max, Eq. 2) and the selected grid index (Eq. 3)."""
+    g = count.shape[0]
+    return _grid_select(lambda j: rank_keys(count[j], mean[j], count[j], mean[j])[:2], g, n_top)

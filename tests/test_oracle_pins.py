@@ -440,3 +440,21 @@ def test_eps_grid_metrics_nested_and_equal_to_the_join():
     sel = O.eps_grid_select(count, mean, 3)
     assert sel["similarity"].shape == (2, 2, 6)
     assert (sel["similarity"][:, 0, 0] == 1.0).all() and (sel["similarity"][:, 1, -1] == 1.0).all()
+
+
+def test_k_grid_metrics_against_the_plain_knn():
+    """Per-k metrics from the k_max lists equal the plain kNN self-join at
+    every k (the lists of smaller k are prefixes, Sec. 3.6.2); in-degree
+    sums to n k; mean kNN distance grows with k."""
+    rng = np.random.default_rng(33)
+    x = rng.random((200, 3))
+    ks = [2, 5, 11, 40]
+    deg, km = O.k_grid_metrics(x, ks)
+    for j, k in enumerate(ks):
+        ref = O.outlier_scores(x, k, 0.1)
+        np.testing.assert_array_equal(deg[j], ref["indeg"])
+        np.testing.assert_allclose(km[j], ref["knn_mean"], rtol=1e-12)
+        assert deg[j].sum() == 200 * k
+    assert (np.diff(km, axis=0) >= -1e-12).all()
+    sel = O.k_grid_select(deg, km, 4)
+    assert (sel["similarity"][:, 0, 0] == 1.0).all() and (sel["similarity"][:, 1, -1] == 1.0).all()
