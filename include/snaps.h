@@ -338,6 +338,38 @@ size_t snaps_eps_grid_workspace(const snaps_eps_grid_job* jobs, int32_t n_jobs);
  * list is host memory, read during the call.  Asynchronous on stream. */
 int snaps_eps_grid(const snaps_eps_grid_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * k between under- and overfitting (paper Sec. 3.6.2, with Eq. 2-3 as in
+ * Sec. 3.5.2).  For an ascending grid k_1 < .. < k_g (the paper: k_min = 2 to
+ * k_max = 4096, sampled finely at small k): the in-degree and the mean kNN
+ * distance of every object at every k (from the k_g nearest neighbours of
+ * every object, which hold those of every smaller k; ties of distance go to
+ * the lower id), the rankings of both metrics at every k, the similarity
+ * (Eq. 2) of each ranking's top n (in rank, then id order) to those of k_1
+ * (U^min) and k_g (U^max), and the index of the k minimising |U^min - U^max|
+ * (the first of equal gaps).  Metric 0 is the in-degree (ascending), metric 1
+ * the mean kNN distance (descending) (Sec. 3.6.1). */
+#define SNAPS_MAX_KGRID_N 32768      /* largest population of a k-grid job */
+#define SNAPS_MAX_KGRID_K 4096       /* largest k of a k grid */
+typedef struct {
+    const snaps_population* pop;   /* columns 16-byte aligned and ld a multiple of 4, as for the eps grid;
+                                      n in [2, SNAPS_MAX_KGRID_N] */
+    uint32_t mask;                 /* subspace */
+    int32_t n_grid;                /* 2..SNAPS_MAX_GRID */
+    int32_t k[SNAPS_MAX_GRID];     /* strictly ascending, k_1 >= 1, k_g <= min(SNAPS_MAX_KGRID_K, n - 1) */
+    int32_t top_n;                 /* n of Eq. 2, 1..n (the paper: 1 % of the population) */
+    int32_t* indeg;                /* [n_grid][n] device or NULL: in-degree per object and k */
+    float* knn_mean;               /* [n_grid][n] device or NULL: mean distance to the k nearest */
+    float* similarity;             /* [2][2][n_grid] device: per metric, U^min then U^max */
+    int32_t* select;               /* [2] device: selected grid index per metric */
+} snaps_k_grid_job;
+
+/* Workspace bytes of snaps_k_grid for these jobs (0 if a job is invalid). */
+size_t snaps_k_grid_workspace(const snaps_k_grid_job* jobs, int32_t n_jobs);
+/* Selection for every job (any mix of populations and subspaces).  The job
+ * list is host memory, read during the call.  Asynchronous on stream. */
+int snaps_k_grid(const snaps_k_grid_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

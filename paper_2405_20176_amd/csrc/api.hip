@@ -1318,3 +1318,162 @@ int snaps_eps_grid(const snaps_eps_grid_job* jobs, int32_t n_jobs, void* ws, siz
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ k grid
+
+namespace {
+
+struct KGridPlan {
+    std::vector<int> d, words;
+    size_t table = 0, gtable = 0, prefix = 0, bytes = 0;
+    std::vector<size_t> thr_off, indeg_off, kmean_off, member_off;
+};
+
+int plan_kgrid(const snaps_k_grid_job* jobs, int32_t n_jobs, KGridPlan* p) {
+    if (n_jobs < 1 || !jobs) return fail(SNAPS_EINVAL, "need at least one k-grid job");
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += align_up(b);
+        return o;
+    };
+    p->table = take((size_t)n_jobs * sizeof(KGridJob));
+    p->gtable = take((size_t)n_jobs * sizeof(GridJob));
+    p->prefix = take((size_t)2 * (n_jobs + kMaxD + 2) * sizeof(int32_t));
+    int64_t queries = 0, tiles = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const snaps_k_grid_job& j = jobs[i];
+        int rc = check_population(j.pop, j.mask);
+        if (rc != SNAPS_OK) return fail(rc, "k-grid job %d: %s", i, g_error.c_str());
+        const int64_t n = j.pop->n;
+        if ((reinterpret_cast<uintptr_t>(j.pop->cols) & 15u) != 0 || (j.pop->ld & 3) != 0)
+            return fail(SNAPS_EINVAL, "k-grid job %d: columns must be 16-byte aligned with ld a multiple of 4", i);
+        if (n < 2 || n > kMaxKGridN)
+            return fail(SNAPS_EUNSUPPORTED, "k-grid job %d: n = %lld outside [2, %d]", i, (long long)n, kMaxKGridN);
+        if (j.n_grid < 2 || j.n_grid > kMaxGrid)
+            return fail(SNAPS_EINVAL, "k-grid job %d: n_grid must be in [2, %d]", i, kMaxGrid);
+        for (int g = 0; g < j.n_grid; ++g) {
+            if (j.k[g] < 1 || (g > 0 && j.k[g] <= j.k[g - 1]))
+                return fail(SNAPS_EINVAL, "k-grid job %d: k must be >= 1 and strictly ascending", i);
+        }
+        const int kmax = j.k[j.n_grid - 1];
+        if (kmax > kMaxKGridK || kmax > n - 1)
+            return fail(SNAPS_EINVAL, "k-grid job %d: k_max = %d exceeds min(%d, n - 1)", i, kmax, kMaxKGridK);
+        if (j.top_n < 1 || j.top_n > n) return fail(SNAPS_EINVAL, "k-grid job %d: top_n must be in [1, n]", i);
+        if (!j.similarity || !j.select) return fail(SNAPS_EINVAL, "k-grid job %d: similarity and select are required", i);
+        p->d.push_back(popcount32(j.mask));
+        const int words = (int)((n + 31) / 32);
+        p->words.push_back(words);
+        p->thr_off.push_back(take((size_t)n * kMaxGrid * sizeof(uint64_t)));
+        p->indeg_off.push_back(j.indeg ? 0 : take((size_t)j.n_grid * n * sizeof(int32_t)));
+        p->kmean_off.push_back(j.knn_mean ? 0 : take((size_t)j.n_grid * n * sizeof(float)));
+        p->member_off.push_back(take((size_t)2 * j.n_grid * words * sizeof(uint32_t)));
+        queries += n;
+        tiles += (n + kTile - 1) / kTile;
+    }
+    if (queries > INT32_MAX) return fail(SNAPS_EUNSUPPORTED, "too many objects in one call");
+    p->bytes = off;
+    return SNAPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t snaps_k_grid_workspace(const snaps_k_grid_job* jobs, int32_t n_jobs) {
+    KGridPlan p;
+    if (plan_kgrid(jobs, n_jobs, &p) != SNAPS_OK) return 0;
+    return p.bytes;
+}
+
+int snaps_k_grid(const snaps_k_grid_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes, void* stream) {
+    KGridPlan p;
+    int rc = plan_kgrid(jobs, n_jobs, &p);
+    if (rc != SNAPS_OK) return rc;
+    if (!ws) return fail(SNAPS_EINVAL, "workspace is NULL (%zu bytes needed)", p.bytes);
+    if (ws_bytes < p.bytes) return fail(SNAPS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, p.bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    std::vector<KGridJob> table;
+    std::vector<GridJob> gtable;
+    table.reserve(n_jobs);
+    gtable.reserve(n_jobs);
+    std::vector<int32_t> qprefix, tprefix;
+    struct Group { int d, first, count, queries, tiles, prefix_at; };
+    std::vector<Group> groups;
+    for (int d = 2; d <= kMaxD; ++d) {
+        Group g{d, (int)table.size(), 0, 0, 0, (int)qprefix.size()};
+        qprefix.push_back(0);
+        tprefix.push_back(0);
+        for (int i = 0; i < n_jobs; ++i) {
+            if (p.d[i] != d) continue;
+            const snaps_k_grid_job& j = jobs[i];
+            const int32_t n = (int32_t)j.pop->n;
+            KGridJob e{};
+            e.cols = j.pop->cols;
+            e.ld = j.pop->ld;
+            e.n = n;
+            e.d = d;
+            int f = 0;
+            for (int b = 0; b < 32; ++b)
+                if ((j.mask >> b) & 1u) e.feat[f++] = b;
+            e.g = j.n_grid;
+            for (int r = 0; r < kMaxGrid; ++r) e.k[r] = j.k[r < j.n_grid ? r : j.n_grid - 1];
+            e.thr = reinterpret_cast<uint64_t*>(base + p.thr_off[i]);
+            e.indeg = j.indeg ? j.indeg : reinterpret_cast<int32_t*>(base + p.indeg_off[i]);
+            e.kmean = j.knn_mean ? j.knn_mean : reinterpret_cast<float*>(base + p.kmean_off[i]);
+            table.push_back(e);
+            GridJob s2{};
+            s2.cols = e.cols;
+            s2.ld = e.ld;
+            s2.n = n;
+            s2.d = d;
+            s2.g = j.n_grid;
+            s2.top_n = j.top_n;
+            s2.count = e.indeg;
+            s2.mean = e.kmean;
+            s2.member = reinterpret_cast<uint32_t*>(base + p.member_off[i]);
+            s2.words = p.words[i];
+            s2.knn = 1;
+            s2.similarity = j.similarity;
+            s2.select = j.select;
+            gtable.push_back(s2);
+            g.count += 1;
+            g.queries += n;
+            g.tiles += (n + kTile - 1) / kTile;
+            qprefix.push_back(g.queries);
+            tprefix.push_back(g.tiles);
+        }
+        if (g.count == 0) {
+            qprefix.pop_back();
+            tprefix.pop_back();
+            continue;
+        }
+        groups.push_back(g);
+    }
+    auto& stg = staging();
+    const size_t tb = table.size() * sizeof(KGridJob), gb = gtable.size() * sizeof(GridJob);
+    const size_t pb = qprefix.size() * sizeof(int32_t);
+    stg.resize(tb + gb + 2 * pb);
+    std::memcpy(stg.data(), table.data(), tb);
+    std::memcpy(stg.data() + tb, gtable.data(), gb);
+    std::memcpy(stg.data() + tb + gb, qprefix.data(), pb);
+    std::memcpy(stg.data() + tb + gb + pb, tprefix.data(), pb);
+    hipError_t e = hipMemcpyAsync(base + p.table, stg.data(), tb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + p.gtable, stg.data() + tb, gb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + p.prefix, stg.data() + tb + gb, 2 * pb, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "k-grid table upload");
+    const KGridJob* dt = reinterpret_cast<const KGridJob*>(base + p.table);
+    const GridJob* dg = reinterpret_cast<const GridJob*>(base + p.gtable);
+    const int32_t* dq = reinterpret_cast<const int32_t*>(base + p.prefix);
+    const int32_t* dtp = dq + qprefix.size();
+    for (const Group& g : groups) {
+        e = launch_kgrid(dt + g.first, dq + g.prefix_at, dtp + g.prefix_at, g.count, g.queries, g.tiles, g.d, s);
+        if (e != hipSuccess) return hip_fail(e, "k-grid launch");
+    }
+    e = launch_grid_select(dg, n_jobs, s);
+    if (e != hipSuccess) return hip_fail(e, "k-grid selection launch");
+    return SNAPS_OK;
+}
+
+}  // extern "C"

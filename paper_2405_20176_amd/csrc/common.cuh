@@ -89,16 +89,17 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* tmp, int* total)
     return inc - v + base;
 }
 
-// Ascending bitonic sort of P (a power of two) 32-bit keys in LDS by the
+// Ascending bitonic sort of P (a power of two) unsigned keys in LDS by the
 // whole workgroup.  Ends with a barrier.
-__device__ __forceinline__ void bitonic_sort_lds(uint32_t* buf, int P) {
+template <typename K>
+__device__ __forceinline__ void bitonic_sort_lds(K* buf, int P) {
     for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int p = threadIdx.x; p < (P >> 1); p += blockDim.x) {
                 const int i = 2 * p - (p & (j - 1));
                 const int l = i + j;
-                const uint32_t a = buf[i];
-                const uint32_t b = buf[l];
+                const K a = buf[i];
+                const K b = buf[l];
                 const bool up = (i & k) == 0;
                 if ((a > b) == up) {
                     buf[i] = b;

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(64) void k_grid_join(const GridJob* jobs, const int
 __device__ __forceinline__ uint32_t grid_key(const GridJob& J, int metric, int j, int64_t i) {
     const int32_t c = J.count[(int64_t)j * J.n + i];
     if (metric == 0) return (uint32_t)c;
-    return ~asc_key(c > 0 ? J.mean[(int64_t)j * J.n + i] : INFINITY);
+    return ~asc_key(c > 0 || J.knn ? J.mean[(int64_t)j * J.n + i] : INFINITY);
 }
 
 // Top n of one (job, radius, metric): radix selection of the n-th smallest

@@ -214,9 +214,26 @@ struct GridJob {
     float* mean;             // [g][n] mean neighbour distance
     uint32_t* member;        // [2][g][words] top-n bit sets (scratch)
     int32_t words;           // ceil(n / 32)
-    int32_t pad0;
+    int32_t knn;             // 1: k grid (count = in-degree, mean = mean kNN distance, ranked without
+                             // the no-neighbour rule of the range join)
     float* similarity;       // [2][2][g] U^min, U^max per metric
     int32_t* select;         // [2] selected radius index per metric
+};
+
+// k selection on a grid of k (one job = one subspace and grid).
+constexpr int kMaxKGridN = 32768;     // distances of one query held in LDS
+constexpr int kMaxKGridK = 4096;
+struct KGridJob {
+    const float* cols;       // 16-byte aligned columns, ld a multiple of 4
+    int64_t ld;
+    int32_t n, d;
+    int32_t feat[kMaxD];
+    int32_t g;
+    int32_t pad0;
+    int32_t k[kMaxGrid];     // strictly ascending, k[g - 1] < n
+    uint64_t* thr;           // [n][kMaxGrid] (distance bits << 32 | id) of the k_j-th neighbour of each object
+    float* kmean;            // [g][n] mean distance to the k_j nearest
+    int32_t* indeg;          // [g][n]
 };
 
 struct RankArgs {
@@ -235,6 +252,10 @@ hipError_t launch_rank(const RankArgs& a, hipStream_t s);
 hipError_t launch_grid_join(const GridJob* jobs, const int32_t* tile_prefix, int n_jobs, int total_tiles, int d,
                             hipStream_t s);
 hipError_t launch_grid_select(const GridJob* jobs, int n_jobs, hipStream_t s);
+// k grid: per-query thresholds and means, then in-degrees; jobs of one d,
+// query_prefix / tile_prefix [n_jobs + 1] by queries and by 64-object tiles.
+hipError_t launch_kgrid(const KGridJob* jobs, const int32_t* query_prefix, const int32_t* tile_prefix, int n_jobs,
+                        int total_queries, int total_tiles, int d, hipStream_t s);
 hipError_t launch_eps_sample(const EpsJob* jobs, const int32_t* prefix, int n_jobs, int total_blocks, int d,
                              hipStream_t s);
 // Mean of the four ranks of every object of every job with an ensemble

@@ -82,6 +82,12 @@ class c_eps_grid_job(ctypes.Structure):
                 ("mean", ctypes.c_void_p), ("similarity", ctypes.c_void_p), ("select", ctypes.c_void_p)]
 
 
+class c_k_grid_job(ctypes.Structure):
+    _fields_ = [("pop", ctypes.POINTER(c_population)), ("mask", ctypes.c_uint32), ("n_grid", ctypes.c_int32),
+                ("k", ctypes.c_int32 * MAX_GRID), ("top_n", ctypes.c_int32), ("indeg", ctypes.c_void_p),
+                ("knn_mean", ctypes.c_void_p), ("similarity", ctypes.c_void_p), ("select", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -132,6 +138,9 @@ def load_library(path: str = LIB_PATH):
     lib.snaps_eps_grid_workspace.argtypes = [P(c_eps_grid_job), i32]
     lib.snaps_eps_grid.restype = ctypes.c_int
     lib.snaps_eps_grid.argtypes = [P(c_eps_grid_job), i32, vp, sz, vp]
+    lib.snaps_k_grid_workspace.argtypes = [P(c_k_grid_job), i32]
+    lib.snaps_k_grid_workspace.restype = sz
+    lib.snaps_k_grid.argtypes = [P(c_k_grid_job), i32, vp, sz, vp]
     _lib = lib
     return lib
 
@@ -478,4 +487,41 @@ def snaps_eps_grid(specs, with_metrics: bool = False, stream=None):
         _check(lib.snaps_eps_grid(arr, len(specs), None, 0, _stream(stream)))
     ws = _workspace(need, outs[0]["select"].device)
     _check(lib.snaps_eps_grid(arr, len(specs), _ptr(ws), ws.numel(), _stream(stream)))
+    return outs
+
+
+def snaps_k_grid(specs, with_metrics: bool = False, stream=None):
+    """k selection on grids of k (Sec. 3.6.2).  ``specs``: sequence of
+    (Population, mask, ks, top_n).  Returns per spec a dict with
+    ``similarity`` [2, 2, g] (metric: in-degree, mean kNN distance; U^min,
+    U^max), ``select`` [2] and, with ``with_metrics``, ``indeg`` /
+    ``knn_mean`` [g, n] (CUDA tensors)."""
+    lib = load_library()
+    arr = (c_k_grid_job * len(specs))()
+    outs = []
+    for i, (pop, mask, ks, top_n) in enumerate(specs):
+        ks = [int(k) for k in ks]
+        g = len(ks)
+        dev = pop.cols.device
+        o = {"similarity": torch.empty((2, 2, g), dtype=torch.float32, device=dev),
+             "select": torch.empty(2, dtype=torch.int32, device=dev)}
+        if with_metrics:
+            o["indeg"] = torch.empty((g, pop.n), dtype=torch.int32, device=dev)
+            o["knn_mean"] = torch.empty((g, pop.n), dtype=torch.float32, device=dev)
+        arr[i].pop = ctypes.pointer(pop.c)
+        arr[i].mask = int(mask)
+        arr[i].n_grid = g
+        for r, v in enumerate(ks[:MAX_GRID]):
+            arr[i].k[r] = v
+        arr[i].top_n = int(top_n)
+        arr[i].indeg = o["indeg"].data_ptr() if with_metrics else None
+        arr[i].knn_mean = o["knn_mean"].data_ptr() if with_metrics else None
+        arr[i].similarity = o["similarity"].data_ptr()
+        arr[i].select = o["select"].data_ptr()
+        outs.append(o)
+    need = lib.snaps_k_grid_workspace(arr, len(specs))
+    if need == 0:
+        _check(lib.snaps_k_grid(arr, len(specs), None, 0, _stream(stream)))
+    ws = _workspace(need, outs[0]["select"].device)
+    _check(lib.snaps_k_grid(arr, len(specs), _ptr(ws), ws.numel(), _stream(stream)))
     return outs

@@ -667,3 +667,100 @@ def test_eps_grid_batched_equals_single_and_degenerate_top(S):
     # top n = every object: every list is the whole population, all gaps are 0
     allt = S.snaps_eps_grid([(pops[0], 0b111, [0.05, 0.1, 0.2], pops[0].n)])[0]
     assert (allt["similarity"] == 1).all() and (allt["select"] == 0).all()
+
+
+def _knn_gap_exempt(P, ks):
+    """Per k of the grid, queries whose k-th and (k+1)-th float64 distances
+    lie within tau (relative) of each other and are not exact duplicates."""
+    D = O.pair_distances(P, P)
+    np.fill_diagonal(D, np.inf)
+    Ds = np.sort(D, axis=1)
+    out = []
+    for k in ks:
+        dk = Ds[:, k - 1]
+        dn = Ds[:, k] if k < P.shape[0] - 1 else np.full(P.shape[0], np.inf)
+        gap = np.where(np.isinf(dn), np.inf, (dn - dk) / np.where(dn > 0, dn, 1.0))
+        out.append(~((gap > TAU) | ((dk == 0) & (dn == 0))))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("d", [2, 5, 9])
+def test_k_grid_against_oracle(S, d):
+    """In-degrees and mean kNN distances at every k meet the oracle (exact
+    in-degrees where no query sits on a near-tie at that k); the similarity
+    curves and selected k are exactly the oracle's selection applied to the
+    GPU's own per-k metrics, and the in-degree choice equals the oracle's
+    outright when the in-degrees agree."""
+    rng = np.random.default_rng(80 + d)
+    n = 1500
+    x = rng.random((n, 16)).astype(np.float32)
+    mask = int(sum(1 << f for f in rng.choice(16, size=d, replace=False)))
+    P = O.project(x, mask).astype(np.float32)
+    ks = [2, 3, 4, 6, 8, 12, 16, 24, 32, 64, 128, 256]
+    top = 15
+    pop = S.Population.from_rows(x)
+    out = S.snaps_k_grid([(pop, mask, ks, top)], with_metrics=True)[0]
+    deg = out["indeg"].cpu().numpy().astype(np.int64)
+    km = out["knn_mean"].cpu().numpy()
+    rd, rk = O.k_grid_metrics(P, ks)
+    ex = _knn_gap_exempt(P, ks)
+    for j, k in enumerate(ks):
+        assert deg[j].sum() == n * k, k
+        if not ex[j].any():
+            assert (deg[j] == rd[j]).all(), k
+        else:
+            assert np.abs(deg[j] - rd[j]).sum() <= 2 * int(ex[j].sum()) * k, k
+        rel = np.abs(km[j] - rk[j]) / np.maximum(rk[j], 1e-30)
+        assert (rel <= TAU).all(), (k, float(rel.max()))
+    assert (np.diff(km, axis=0) >= 0).all()            # more neighbours, farther on average
+    mine = O.k_grid_select(deg, km.astype(np.float64), top)
+    np.testing.assert_array_equal(out["similarity"].cpu().numpy(), mine["similarity"].astype(np.float32))
+    np.testing.assert_array_equal(out["select"].cpu().numpy(), mine["select"])
+    if (deg == rd).all():
+        ref = O.k_grid_select(rd, rk, top)
+        assert int(out["select"].cpu().numpy()[0]) == int(ref["select"][0])
+
+
+def test_k_grid_ties_duplicates_and_every_neighbour(S):
+    """Coordinates on a 1/8 grid: every squared distance is exact in float32
+    and float64, so ties (and duplicates at distance 0) are resolved by id on
+    both sides and the in-degrees must agree exactly at every k, up to
+    k = n - 1 (every other object)."""
+    rng = np.random.default_rng(5)
+    n = 300
+    x = (rng.integers(0, 6, size=(n, 4)) / 8.0).astype(np.float32)
+    mask = 0b1111
+    P = O.project(x, mask).astype(np.float32)
+    ks = [1, 2, 5, 17, 100, n - 1]
+    out = S.snaps_k_grid([(S.Population.from_rows(x), mask, ks, 10)], with_metrics=True)[0]
+    deg = out["indeg"].cpu().numpy().astype(np.int64)
+    km = out["knn_mean"].cpu().numpy()
+    rd, rk = O.k_grid_metrics(P, ks)
+    np.testing.assert_array_equal(deg, rd)
+    assert (deg[-1] == n - 1).all()
+    rel = np.abs(km - rk) / np.maximum(rk, 1e-30)
+    assert ((rel <= TAU) | ((rk == 0) & (km == 0))).all()
+    mine = O.k_grid_select(deg, km.astype(np.float64), 10)
+    np.testing.assert_array_equal(out["select"].cpu().numpy(), mine["select"])
+
+
+def test_k_grid_batched_equals_single_and_degenerate_top(S):
+    rng = np.random.default_rng(19)
+    pops = [S.Population.from_rows(rng.random((n, 15)).astype(np.float32)) for n in (700, 1301)]
+    specs = []
+    for i in range(8):
+        pop = pops[i % 2]
+        d = int(rng.integers(2, 16))
+        mask = int(sum(1 << f for f in rng.choice(15, size=d, replace=False)))
+        ks = sorted(set(int(v) for v in rng.integers(1, 400, size=int(rng.integers(2, 17)))))
+        if len(ks) < 2:
+            ks = [1, 400]
+        specs.append((pop, mask, ks, max(1, pop.n // 100)))
+    batched = S.snaps_k_grid(specs, with_metrics=True)
+    for spec, b in zip(specs, batched):
+        single = S.snaps_k_grid([spec], with_metrics=True)[0]
+        for key in ("similarity", "select", "indeg", "knn_mean"):
+            assert torch.equal(single[key], b[key]), key
+    # top n = every object: every list is the whole population, all gaps are 0
+    allt = S.snaps_k_grid([(pops[0], 0b111, [2, 10, 50], pops[0].n)])[0]
+    assert (allt["similarity"] == 1).all() and (allt["select"] == 0).all()
