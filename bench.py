@@ -245,6 +245,38 @@ def eps_grid_bench(S, pop, masks, n, dev, spaces: int = 1024, g: int = 16, m: in
             "clock": "host wall clock around sampler + grid calls (includes table uploads and the radii copy)"}
 
 
+# The paper's k grid runs from k_min = 2 to k_max = 4096 and is sampled
+# finely at small k, where the choice falls (Sec. 3.6.2).
+K_GRID = [2, 3, 4, 6, 8, 11, 16, 23, 32, 45, 64, 128, 256, 512, 1024, 4096]
+
+
+def k_grid_bench(S, pop, masks, n, dev, spaces: int = 1024):
+    """The paper's k selection (Sec. 3.6.2) on an evenly spaced slice of the
+    subspaces: in-degree and mean kNN distance at every k of K_GRID, the
+    per-k rankings and the Eq. 3 choice for both KNNSJ metrics, top n = 1 %
+    of the population."""
+    import torch
+    idx = np.linspace(0, len(masks) - 1, min(spaces, len(masks))).astype(int)
+    top = max(1, int(round(0.01 * n)))
+    ks = [k for k in K_GRID if k <= n - 1]
+    specs = [(pop, int(masks[i]), ks, top) for i in idx]
+    S.snaps_k_grid(specs[:1])                       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = S.snaps_k_grid(specs)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    sel = torch.stack([o["select"] for o in outs]).cpu().numpy()
+    full = sec * len(masks) / len(idx)
+    log(f"k-grid selection: {len(idx)} subspaces in {sec:.2f} s")
+    return {"seconds": sec, "subspaces": len(idx), "grid": ks, "top_n": top,
+            "seconds_per_subspace": sec / len(idx), "extrapolated_all_subspaces_s": full,
+            "pairs_per_subspace": float(n) * (n - 1),
+            "selected_k_median": [float(np.median(np.asarray(ks)[sel[:, 0]])),
+                                  float(np.median(np.asarray(ks)[sel[:, 1]]))],
+            "clock": "host wall clock around one k-grid call (includes the table upload)"}
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -286,6 +318,10 @@ def main():
                     help="skip timing the sampled eps_min / eps_max radii of every subspace")
     ap.add_argument("--no-eps-grid", dest="eps_grid", action="store_false",
                     help="skip timing the eps-grid selection on a slice of the subspaces")
+    ap.add_argument("--no-k-grid", dest="k_grid", action="store_false",
+                    help="skip timing the k-grid selection on a slice of the subspaces")
+    ap.add_argument("--grid-spaces", type=int, default=1024,
+                    help="subspaces in the eps-grid and k-grid slices")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain MIB-MiB device copy (counter calibration) and exit")
     a = ap.parse_args()
@@ -462,7 +498,9 @@ def main():
     if a.eps_sampler:
         result["eps_sampler"] = eps_sampler_bench(S, pop, masks, n, dev)
     if a.eps_grid:
-        result["eps_grid_selection"] = eps_grid_bench(S, pop, masks, n, dev)
+        result["eps_grid_selection"] = eps_grid_bench(S, pop, masks, n, dev, spaces=a.grid_spaces)
+    if a.k_grid:
+        result["k_grid_selection"] = k_grid_bench(S, pop, masks, n, dev, spaces=a.grid_spaces)
 
     if a.serve_seconds > 0:
         del plans

@@ -1440,7 +1440,8 @@ int snaps_k_grid(const snaps_k_grid_job* jobs, int32_t n_jobs, void* ws, size_t 
             gtable.push_back(s2);
             g.count += 1;
             g.queries += n;
-            g.tiles += (n + kTile - 1) / kTile;
+            const int tg = kgrid_tiles_per_group();
+            g.tiles += ((n + kTile - 1) / kTile + tg - 1) / tg;      // groups of tiles
             qprefix.push_back(g.queries);
             tprefix.push_back(g.tiles);
         }

@@ -64,6 +64,40 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
     return v;
 }
 
+// Inclusive scan over a 64-lane wavefront with DPP row shifts and row
+// broadcasts (no LDS traffic): shifts by 1, 2, 4 and 8 within each row of 16
+// lanes, then row 0's last lane into row 1 (and row 2's into row 3), then
+// lane 31 into rows 2 and 3.  Lanes with no source add 0.
+__device__ __forceinline__ int wave_scan_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+    return v;
+}
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_move_f64(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, kCtrl, kRowMask, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), kCtrl, kRowMask, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// The same scan on doubles (both halves moved by DPP); lane 63 ends with
+// the sum over the wavefront.
+__device__ __forceinline__ double wave_scan_dpp(double v) {
+    v += dpp_move_f64<0x111, 0xf>(v);
+    v += dpp_move_f64<0x112, 0xf>(v);
+    v += dpp_move_f64<0x114, 0xf>(v);
+    v += dpp_move_f64<0x118, 0xf>(v);
+    v += dpp_move_f64<0x142, 0xa>(v);
+    v += dpp_move_f64<0x143, 0xc>(v);
+    return v;
+}
+
 // Exclusive scan over the whole workgroup (blockDim.x a multiple of 64,
 // at most 1024).  tmp needs 17 ints of LDS.  Returns the exclusive prefix
 // and writes the workgroup total to *total.  Contains three barriers, so

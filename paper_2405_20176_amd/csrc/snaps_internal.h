@@ -253,9 +253,11 @@ hipError_t launch_grid_join(const GridJob* jobs, const int32_t* tile_prefix, int
                             hipStream_t s);
 hipError_t launch_grid_select(const GridJob* jobs, int n_jobs, hipStream_t s);
 // k grid: per-query thresholds and means, then in-degrees; jobs of one d,
-// query_prefix / tile_prefix [n_jobs + 1] by queries and by 64-object tiles.
-hipError_t launch_kgrid(const KGridJob* jobs, const int32_t* query_prefix, const int32_t* tile_prefix, int n_jobs,
-                        int total_queries, int total_tiles, int d, hipStream_t s);
+// query_prefix / group_prefix [n_jobs + 1] by queries and by groups of
+// kgrid_tiles_per_group() 64-object tiles.
+int kgrid_tiles_per_group();
+hipError_t launch_kgrid(const KGridJob* jobs, const int32_t* query_prefix, const int32_t* group_prefix, int n_jobs,
+                        int total_queries, int total_groups, int d, hipStream_t s);
 hipError_t launch_eps_sample(const EpsJob* jobs, const int32_t* prefix, int n_jobs, int total_blocks, int d,
                              hipStream_t s);
 // Mean of the four ranks of every object of every job with an ensemble
