@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kThreshThreads = 1024;
 constexpr int kSlots = kMaxKGridN / kThreshThreads;   // distances per thread, in registers
+constexpr int kLookupBatch = 8;
 
 __device__ __forceinline__ int kjob_of(const int32_t* prefix, int n_jobs, int b) {
     int lo = 0, hi = n_jobs;
@@ -185,13 +186,16 @@ __global__ __launch_bounds__(kThreshThreads) void k_kgrid_thresh(const KGridJob*
     }
     for (int x = tid; x < kMaxGrid * 1024; x += kThreshThreads) hist[x] = 0u;
     __syncthreads();
+    // Table reads batched ahead of the increments (slots past n read the
+    // empty entry of their 0xFFFFFFFF).
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-        if (s * kThreshThreads < n) {
-            const uint32_t v = e[s];
-            const unsigned g1 = tab1[v >> 20];
-            if (g1) atomicAdd(&hist[(g1 - 1u) * 1024u + ((v >> 10) & 1023u)], 1u);
-        }
+    for (int s0 = 0; s0 < kSlots; s0 += kLookupBatch) {
+        unsigned g1[kLookupBatch];
+#pragma unroll
+        for (int u = 0; u < kLookupBatch; ++u) g1[u] = tab1[e[s0 + u] >> 20];
+#pragma unroll
+        for (int u = 0; u < kLookupBatch; ++u)
+            if (g1[u]) atomicAdd(&hist[(g1[u] - 1u) * 1024u + ((e[s0 + u] >> 10) & 1023u)], 1u);
     }
     __syncthreads();
     {
@@ -213,15 +217,16 @@ __global__ __launch_bounds__(kThreshThreads) void k_kgrid_thresh(const KGridJob*
     for (int x = tid; x < kMaxGrid * 1024; x += kThreshThreads) hist[x] = 0u;
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-        if (s * kThreshThreads < n) {
-            const uint32_t v = e[s];
-            const unsigned g1 = tab1[v >> 20];
-            if (g1) {
-                const unsigned g2 = tab2[g1 - 1u][(v >> 10) & 1023u];
-                if (g2) atomicAdd(&hist[(g2 - 1u) * 1024u + (v & 1023u)], 1u);
-            }
-        }
+    for (int s0 = 0; s0 < kSlots; s0 += kLookupBatch) {
+        unsigned g1[kLookupBatch], g2[kLookupBatch];
+#pragma unroll
+        for (int u = 0; u < kLookupBatch; ++u) g1[u] = tab1[e[s0 + u] >> 20];
+#pragma unroll
+        for (int u = 0; u < kLookupBatch; ++u)
+            g2[u] = tab2[g1[u] ? g1[u] - 1u : 0u][(e[s0 + u] >> 10) & 1023u];
+#pragma unroll
+        for (int u = 0; u < kLookupBatch; ++u)
+            if (g1[u] && g2[u]) atomicAdd(&hist[(g2[u] - 1u) * 1024u + (e[s0 + u] & 1023u)], 1u);
     }
     __syncthreads();
     {
@@ -295,17 +300,20 @@ __global__ __launch_bounds__(kThreshThreads) void k_kgrid_thresh(const KGridJob*
 #pragma unroll
         for (int t = 0; t < kMaxGrid; ++t) part[t] += c == t ? dv : 0.0;
     }
+    {
+        double run = 0.0;                           // lane 63: this wavefront's sums of bins 0..t
 #pragma unroll
-    for (int t = 0; t < kMaxGrid; ++t) {
-        const double w = wave_scan_dpp(part[t]);
-        if (lane == 63) s_part[wave][t] = w;
+        for (int t = 0; t < kMaxGrid; ++t) {
+            run += wave_scan_dpp(part[t]);
+            if (lane == 63) s_part[wave][t] = run;
+        }
     }
     __syncthreads();
     if (tid < kMaxGrid) {
         const int t = tid;
-        double sum = 0.0;                           // distances below target t's: bins 0..t
-        for (int c = 0; c <= t; ++c)
-            for (int w = 0; w < kThreshThreads / 64; ++w) sum += s_part[w][c];
+        double sum = 0.0;                           // distances below target t's
+#pragma unroll
+        for (int w = 0; w < kThreshThreads / 64; ++w) sum += s_part[w][t];
         sum += (double)s_rank[t] * (double)sqrtf(__uint_as_float(vt[t]));
         J.thr[(int64_t)qid * kMaxGrid + t] = ((uint64_t)vt[t] << 32) | (uint64_t)s_id[t];
         if (t < g) J.kmean[(int64_t)t * n + qid] = (float)(sum / (double)J.k[t]);
