@@ -102,15 +102,18 @@ __device__ void eps_next_body(const EpsJob& J, int s) {
 
 template <int D>
 __global__ __launch_bounds__(kEpsThreads) void k_eps_hist(const EpsJob* jobs, const int32_t* prefix, int n_jobs,
-                                                          int pass) {
-    const int j = eps_job_of(prefix, n_jobs, blockIdx.x);
-    eps_hist_body<D>(jobs[j], blockIdx.x - prefix[j], pass);
+                                                          int pass, int block0) {
+    const int b = block0 + (int)blockIdx.x;
+    const int j = eps_job_of(prefix, n_jobs, b);
+    eps_hist_body<D>(jobs[j], b - prefix[j], pass);
 }
 
 template <int D>
-__global__ __launch_bounds__(kEpsThreads) void k_eps_next(const EpsJob* jobs, const int32_t* prefix, int n_jobs) {
-    const int j = eps_job_of(prefix, n_jobs, blockIdx.x);
-    eps_next_body<D>(jobs[j], blockIdx.x - prefix[j]);
+__global__ __launch_bounds__(kEpsThreads) void k_eps_next(const EpsJob* jobs, const int32_t* prefix, int n_jobs,
+                                                          int block0) {
+    const int b = block0 + (int)blockIdx.x;
+    const int j = eps_job_of(prefix, n_jobs, b);
+    eps_next_body<D>(jobs[j], b - prefix[j]);
 }
 
 __global__ void k_eps_init(const EpsJob* jobs, int n_jobs) {
@@ -178,8 +181,8 @@ __global__ void k_eps_finish(const EpsJob* jobs, int n_jobs) {
     }
 }
 
-using EpsFn = void (*)(const EpsJob*, const int32_t*, int, int);
-using EpsNextFn = void (*)(const EpsJob*, const int32_t*, int);
+using EpsFn = void (*)(const EpsJob*, const int32_t*, int, int, int);
+using EpsNextFn = void (*)(const EpsJob*, const int32_t*, int, int);
 
 template <int D>
 void eps_fns(EpsFn* h, EpsNextFn* nx) {
@@ -218,12 +221,19 @@ hipError_t launch_eps_sample(const EpsJob* jobs, const int32_t* prefix, int n_jo
     EpsNextFn next;
     if (!eps_pick_d(d, &hist, &next)) return hipErrorInvalidValue;
     if (n_jobs <= 0 || total_blocks <= 0) return hipSuccess;
+    // A dispatch counts its work-items in 32 bits: launches of at most 2^22
+    // workgroups of 256.
+    constexpr int kMaxBlocks = 1 << 22;
     hipLaunchKernelGGL(k_eps_init, dim3(n_jobs), dim3(256), 0, s, jobs, n_jobs);
     for (int pass = 0; pass < 4; ++pass) {
-        hipLaunchKernelGGL(hist, dim3(total_blocks), dim3(kEpsThreads), 0, s, jobs, prefix, n_jobs, pass);
+        for (int b0 = 0; b0 < total_blocks; b0 += kMaxBlocks)
+            hipLaunchKernelGGL(hist, dim3(min(kMaxBlocks, total_blocks - b0)), dim3(kEpsThreads), 0, s, jobs, prefix,
+                               n_jobs, pass, b0);
         hipLaunchKernelGGL(k_eps_pick, dim3(n_jobs), dim3(256), 0, s, jobs, n_jobs, pass);
     }
-    hipLaunchKernelGGL(next, dim3(total_blocks), dim3(kEpsThreads), 0, s, jobs, prefix, n_jobs);
+    for (int b0 = 0; b0 < total_blocks; b0 += kMaxBlocks)
+        hipLaunchKernelGGL(next, dim3(min(kMaxBlocks, total_blocks - b0)), dim3(kEpsThreads), 0, s, jobs, prefix, n_jobs,
+                           b0);
     hipLaunchKernelGGL(k_eps_finish, dim3(n_jobs), dim3(64), 0, s, jobs, n_jobs);
     return hipGetLastError();
 }

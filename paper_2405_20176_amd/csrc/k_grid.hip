@@ -114,7 +114,7 @@ __device__ __forceinline__ void wave_rank_bin(const unsigned* h, int per, unsign
 // nearest are split by id (rare: a separate selection over the ties' ids).
 template <int D>
 __global__ __launch_bounds__(kThreshThreads) void k_kgrid_thresh(const KGridJob* jobs, const int32_t* prefix,
-                                                                  int n_jobs) {
+                                                                  int n_jobs, int block0) {
     static_assert(kThreshThreads == 64 * kMaxGrid, "one wavefront per grid target");
     __shared__ unsigned hist[kMaxGrid * 1024];      // pass 0: one 4096-bin histogram; then [group][1024]
     __shared__ uint8_t tab1[4096];                  // 12-bit digit -> pass-1 group + 1 (0: none)
@@ -126,9 +126,10 @@ __global__ __launch_bounds__(kThreshThreads) void k_kgrid_thresh(const KGridJob*
     __shared__ int tmp[17];
     __shared__ unsigned s_sel[3];
     __shared__ unsigned s_fill;
-    const int jb = kjob_of(prefix, n_jobs, blockIdx.x);
+    const int blk = block0 + (int)blockIdx.x;
+    const int jb = kjob_of(prefix, n_jobs, blk);
     const KGridJob& J = jobs[jb];
-    const int qid = blockIdx.x - prefix[jb];
+    const int qid = blk - prefix[jb];
     const int n = J.n;
     const int g = J.g;
     const int tid = threadIdx.x;
@@ -378,15 +379,16 @@ __global__ __launch_bounds__(64 * kIndegWaves) void k_kgrid_indeg(const KGridJob
         if (t < g) J.indeg[(int64_t)t * n + p] = (int32_t)cnt[t];
 }
 
-using KThreshFn = void (*)(const KGridJob*, const int32_t*, int);
+using KThreshFn = void (*)(const KGridJob*, const int32_t*, int, int);
+using KIndegFn = void (*)(const KGridJob*, const int32_t*, int);
 
 template <int D>
-void kgrid_fns(KThreshFn* a, KThreshFn* b) {
+void kgrid_fns(KThreshFn* a, KIndegFn* b) {
     *a = k_kgrid_thresh<D>;
     *b = k_kgrid_indeg<D>;
 }
 
-bool kgrid_pick(int d, KThreshFn* a, KThreshFn* b) {
+bool kgrid_pick(int d, KThreshFn* a, KIndegFn* b) {
     switch (d) {
         case 2: kgrid_fns<2>(a, b); return true;
         case 3: kgrid_fns<3>(a, b); return true;
@@ -413,10 +415,17 @@ int kgrid_tiles_per_group() { return kIndegWaves; }
 
 hipError_t launch_kgrid(const KGridJob* jobs, const int32_t* query_prefix, const int32_t* group_prefix, int n_jobs,
                         int total_queries, int total_groups, int d, hipStream_t s) {
-    KThreshFn thresh, indeg;
+    KThreshFn thresh;
+    KIndegFn indeg;
     if (!kgrid_pick(d, &thresh, &indeg)) return hipErrorInvalidValue;
     if (n_jobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(thresh, dim3(total_queries), dim3(kThreshThreads), 0, s, jobs, query_prefix, n_jobs);
+    // A dispatch counts its work-items in 32 bits: launches of at most 2^21
+    // workgroups of 1024.
+    constexpr int kMaxBlocks = 1 << 21;
+    for (int b0 = 0; b0 < total_queries; b0 += kMaxBlocks) {
+        const int nb = min(kMaxBlocks, total_queries - b0);
+        hipLaunchKernelGGL(thresh, dim3(nb), dim3(kThreshThreads), 0, s, jobs, query_prefix, n_jobs, b0);
+    }
     hipLaunchKernelGGL(indeg, dim3(total_groups), dim3(64 * kIndegWaves), 0, s, jobs, group_prefix, n_jobs);
     return hipGetLastError();
 }

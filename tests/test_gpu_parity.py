@@ -5,6 +5,7 @@ by element with the oracle under the acceptance rule of ``tests/parity.py``.
 """
 from __future__ import annotations
 
+import itertools
 import math
 
 import numpy as np
@@ -764,3 +765,35 @@ def test_k_grid_batched_equals_single_and_degenerate_top(S):
     # top n = every object: every list is the whole population, all gaps are 0
     allt = S.snaps_k_grid([(pops[0], 0b111, [2, 10, 50], pops[0].n)])[0]
     assert (allt["similarity"] == 1).all() and (allt["select"] == 0).all()
+
+
+def test_k_grid_beyond_one_dispatch(S):
+    """More queries of one dimensionality in one call than one dispatch of
+    1024-wide workgroups can count (2^32 work-items): the last job still
+    equals its own call."""
+    rng = np.random.default_rng(13)
+    n = 32768
+    pop = S.Population.from_rows(rng.random((n, 15)).astype(np.float32))
+    masks = [int(sum(1 << f for f in c)) for c in itertools.islice(itertools.combinations(range(15), 3), 130)]
+    ks = [2, 16, 128]
+    specs = [(pop, m, ks, 100) for m in masks]
+    assert len(specs) * n > (1 << 22)
+    out = S.snaps_k_grid(specs, with_metrics=True)
+    for i in (0, len(specs) - 1):
+        single = S.snaps_k_grid([specs[i]], with_metrics=True)[0]
+        for key in ("similarity", "select", "indeg", "knn_mean"):
+            assert torch.equal(single[key], out[i][key]), (i, key)
+
+
+def test_eps_sampler_beyond_one_dispatch(S):
+    """More sample objects in one call than one dispatch of 256-wide
+    workgroups can count: the first and last jobs equal their own calls."""
+    rng = np.random.default_rng(12)
+    n = 1024
+    pop = S.Population.from_rows(rng.random((n, 15)).astype(np.float32))
+    sample = torch.arange(n, dtype=torch.int32, device="cuda")
+    jobs = (1 << 22) // n + 2
+    specs = [(pop, 0b111 << (i % 12), sample, [0.01 * n, 0.15 * n]) for i in range(jobs)]
+    out = S.snaps_eps_sample(specs)
+    for i in (0, jobs - 1):
+        assert torch.equal(S.snaps_eps_sample([specs[i]])[0], out[i]), i
