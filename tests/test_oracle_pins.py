@@ -458,3 +458,56 @@ def test_k_grid_metrics_against_the_plain_knn():
     assert (np.diff(km, axis=0) >= -1e-12).all()
     sel = O.k_grid_select(deg, km, 4)
     assert (sel["similarity"][:, 0, 0] == 1.0).all() and (sel["similarity"][:, 1, -1] == 1.0).all()
+
+
+def test_k_grid_metrics_against_scipy_kdtree():
+    """In-degree and mean kNN distance at every k of a grid against scipy's
+    cKDTree (k + 1 nearest including self; continuous data, no ties)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(34)
+    x = rng.random((250, 4))
+    ks = [1, 3, 8, 30]
+    deg, km = O.k_grid_metrics(x, ks)
+    dist, ids = cKDTree(x).query(x, k=max(ks) + 1)
+    for j, k in enumerate(ks):
+        nb = ids[:, 1:k + 1]
+        assert (nb != np.arange(250)[:, None]).all()
+        np.testing.assert_array_equal(deg[j], np.bincount(nb.ravel(), minlength=250))
+        np.testing.assert_allclose(km[j], dist[:, 1:k + 1].mean(axis=1), rtol=1e-12)
+
+
+def test_grid_selection_by_hand():
+    """Eq. 2-3 on per-grid-point metrics whose top-2 lists are known by
+    hand.  In-degree (ascending) tops are {0,1}, {1,2}, {2,3}: U^min =
+    (1, .5, 0), U^max = (0, .5, 1), so the middle point is selected.  The
+    mean kNN distance ranks descending: tops {5,6}, {5,7}, {7,8} give U^min =
+    (1, .5, 0), U^max = (0, .5, 1) again.  The radius grid ranks its mean
+    the same way except that objects with no neighbour come first."""
+    n = 10
+    deg = np.full((3, n), 5)
+    deg[0, [0, 1]] = [0, 1]
+    deg[1, [1, 2]] = [0, 1]
+    deg[2, [2, 3]] = [1, 0]
+    km = np.ones((3, n))
+    km[0, [5, 6]] = [3.0, 2.0]
+    km[1, [5, 7]] = [2.0, 3.0]
+    km[2, [7, 8]] = [3.0, 3.0]
+    sel = O.k_grid_select(deg, km, 2)
+    for metric in (0, 1):
+        np.testing.assert_allclose(sel["similarity"][metric, 0], [1.0, 0.5, 0.0])
+        np.testing.assert_allclose(sel["similarity"][metric, 1], [0.0, 0.5, 1.0])
+    assert sel["select"].tolist() == [1, 1]
+    # radius grid: object 9 has no neighbour at the first radius, so it leads
+    # the mean ranking there although its mean is the smallest (0): tops
+    # {9, 5}, {7, 5}, {8, 9} (without that rule the first would be {5, 6}
+    # and U^min_3 would be 0)
+    cnt = np.full((3, n), 4)
+    cnt[0, 9] = 0
+    mean = np.ones((3, n))
+    mean[0, [5, 6, 9]] = [3.0, 2.0, 0.0]
+    mean[1, [5, 7]] = [2.0, 3.0]
+    mean[2, [8, 9]] = [3.0, 3.0]
+    sel = O.eps_grid_select(cnt, mean, 2)
+    np.testing.assert_allclose(sel["similarity"][1, 0], [1.0, 0.5, 0.5])
+    np.testing.assert_allclose(sel["similarity"][1, 1], [0.5, 0.0, 1.0])
+    assert int(sel["select"][1]) == 0
