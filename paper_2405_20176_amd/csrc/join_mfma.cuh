@@ -21,14 +21,14 @@
 // maximum over the accumulators and one ballot establish.  Otherwise the
 // ballot of each accumulator register gives, in its low and high 32 bits,
 // the passing candidates of two queries in one candidate block; those bits
-// are written into the owning lanes' per-query candidate masks, whose union
-// is then walked candidate by candidate in ascending order (a
-// wavefront-uniform loop; the candidate row is read out of the operand
-// registers that already hold it, lane by lane).  Every
-// lane whose mask holds the candidate re-evaluates the exact direct-form
-// distance and updates its query's kNN list and eps sums exactly as k_join
-// does, in the same order, so the results are identical to both k_join
-// flavours.
+// are written into the owning lanes' per-query candidate masks.  The tile's
+// candidate rows go from the operand registers into LDS, and each lane walks
+// its own mask in ascending candidate order: it re-evaluates the exact
+// direct-form distance of each candidate and updates its query's kNN list
+// and eps sums exactly as k_join does, in the same order, so the results
+// are identical to both k_join flavours.  (A wavefront-uniform walk over the
+// union of the masks costs one iteration per distinct candidate; the
+// per-lane walk costs the largest per-query count.)
 #pragma once
 
 #include "join_kernel.cuh"
@@ -59,6 +59,7 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
     constexpr float cq = (float)(2 * (8 * D + 24)) * 5.9604644775390625e-8f;
     __shared__ int s_unit, s_queue;
     __shared__ uint2 s_mask[64];            // per-query candidate masks of one tile pair
+    __shared__ __align__(16) float s_cand[64][DP];   // candidate rows of a tile pair with passes
 
     const int lane = threadIdx.x;
     const int half = lane >> 5;
@@ -172,8 +173,7 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
         typedef const __attribute__((address_space(1))) float* gfloat;
         const gfloat xg = (gfloat)xs_g;
         // The candidate's id bits come along, so that the exact recheck can
-        // take a candidate's row from these registers (v_readlane) instead
-        // of memory.
+        // stage whole candidate rows from these registers.
         auto load_b = [&](int t, float (&br)[2][KSTEPS + 2]) {
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
@@ -241,35 +241,34 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
             if (u_lo | u_hi) {
                 const uint2 mine2 = s_mask[lane];
                 s_mask[lane] = make_uint2(0u, 0u);
+                // The tile's candidate rows into LDS (row 32 cb + col: this
+                // lane's dimensions 2 s + half; the id from lane half 0), so
+                // that each lane reads the rows of its own passing candidates.
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    float* row = &s_cand[32 * cb + col][0];
+#pragma unroll
+                    for (int s2 = 0; s2 < KSTEPS; ++s2)
+                        if (2 * s2 + half < D) row[2 * s2 + half] = br[cb][s2];
+                    if (!half) reinterpret_cast<int*>(row)[D] = __float_as_int(br[cb][KSTEPS + 1]);
+                }
                 bool moved = false;
-                // Candidates of block cb with a passing pair, ascending; the row
-                // of candidate 32 cb + jj: even dimensions in lane jj, odd ones
-                // in lane jj + 32 of the operand registers.
-                auto recheck = [&](auto cbc, unsigned um, unsigned mine) {
-                    constexpr int cb = decltype(cbc)::value;
-                    while (um) {
-                        const int jj = __builtin_ctz(um);
-                        um &= um - 1;
-                        const int c = cbase + 32 * cb + jj;
-                        float pr[D];
+                // This lane's passing candidates in ascending order (block 0,
+                // then block 1): the order in which the direct form meets them.
+                unsigned long long mine = ((unsigned long long)mine2.y << 32) | mine2.x;
+                while (mine) {
+                    const int j = __builtin_ctzll(mine);
+                    mine &= mine - 1;
+                    if (cbase + j == qpos) continue;
+                    const float* row = &s_cand[j][0];
+                    float dd = 0.f;
 #pragma unroll
-                        for (int f = 0; f < D; ++f)
-                            pr[f] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(br[cb][f >> 1]),
-                                                                             jj + 32 * (f & 1)));
-                        const int cid = __builtin_amdgcn_readlane(__float_as_int(br[cb][KSTEPS + 1]), jj);
-                        if (((mine >> jj) & 1u) && c != qpos) {
-                            float dd = 0.f;
-#pragma unroll
-                            for (int f = 0; f < D; ++f) {
-                                const float tq = q[f] - pr[f];
-                                dd = fmaf(tq, tq, dd);
-                            }
-                            if (dd <= thr) moved |= take(dd, cid);
-                        }
+                    for (int f = 0; f < D; ++f) {
+                        const float tq = q[f] - row[f];
+                        dd = fmaf(tq, tq, dd);
                     }
-                };
-                recheck(std::integral_constant<int, 0>{}, u_lo, mine2.x);
-                recheck(std::integral_constant<int, 1>{}, u_hi, mine2.y);
+                    if (dd <= thr) moved |= take(dd, reinterpret_cast<const int*>(row)[D]);
+                }
                 if (__any(moved)) refresh_limits();
             }
         };

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kThreshThreads) void k_kgrid_thresh(const KGridJob*
     __shared__ double s_part[kThreshThreads / 64][kMaxGrid];
     __shared__ int tmp[17];
     __shared__ unsigned s_sel[3];
-    __shared__ unsigned s_fill;
+    __shared__ unsigned s_fill, s_split;
     const int blk = block0 + (int)blockIdx.x;
     const int jb = kjob_of(prefix, n_jobs, blk);
     const KGridJob& J = jobs[jb];
@@ -140,7 +140,10 @@ __global__ __launch_bounds__(kThreshThreads) void k_kgrid_thresh(const KGridJob*
         for (int x = tid; x < 4096 / 4; x += kThreshThreads) t1[x] = 0u;
         for (int x = tid; x < kMaxGrid * 1024 / 4; x += kThreshThreads) t2[x] = 0u;
         for (int x = tid; x < 4096; x += kThreshThreads) hist[x] = 0u;
-        if (tid == 0) s_fill = 0u;
+        if (tid == 0) {
+            s_fill = 0u;
+            s_split = 0u;
+        }
     }
     float q[D];
 #pragma unroll
@@ -238,13 +241,15 @@ __global__ __launch_bounds__(kThreshThreads) void k_kgrid_thresh(const KGridJob*
             s_rank[wave] -= below;
             s_eq[wave] = size;
             s_id[wave] = 0xFFFFFFFFu;               // every tie at the distance belongs
+            if (size > s_rank[wave]) atomicOr(&s_split, 1u << wave);
         }
     }
     __syncthreads();
-    // Ties split by id: the s_rank-th smallest id among the ties.
-    for (int t = 0; t < kMaxGrid; ++t) {
+    // Ties split by id (targets in s_split): the s_rank-th smallest id among
+    // the ties.
+    for (unsigned todo = s_split; todo; todo &= todo - 1u) {
+        const int t = __builtin_ctz(todo);
         const unsigned vt = s_pre[t], rt = s_rank[t];
-        if (s_eq[t] <= rt) continue;                // uniform
         if (t > 0 && vt == s_pre[t - 1] && rt == s_rank[t - 1]) {
             if (tid == 0) s_id[t] = s_id[t - 1];
             __syncthreads();
