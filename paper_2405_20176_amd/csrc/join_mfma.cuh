@@ -60,6 +60,8 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
     __shared__ int s_unit, s_queue;
     __shared__ uint2 s_mask[64];            // per-query candidate masks of one tile pair
     __shared__ __align__(16) float s_cand[64][DP];   // candidate rows of a tile pair with passes
+    constexpr int kRowShift = 28;           // walk entries: tile index | reachable block rows << 28
+    constexpr int kTileMask = (1 << kRowShift) - 1;
 
     const int lane = threadIdx.x;
     const int half = lane >> 5;
@@ -147,13 +149,15 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
         };
 
         // Next candidate tile of the walk whose box may hold a candidate
-        // (or -1 at the end); advances the walk position ws.
+        // (or -1 at the end); advances the walk position ws.  Bits 28-29 of
+        // the result flag the 32-query block rows with a query that may reach
+        // the box (the other block row's contraction is skipped).
         int ws = 0;
         auto next_tile = [&]() -> int {
             while (ws < nt) {
                 const int t = spiral(t0, ws, nt);
                 ++ws;
-                if (!prune) return t;
+                if (!prune) return t | (3 << kRowShift);
                 cptr<float> bx = boxes + (int64_t)t * 2 * DP;
                 float lb = 0.f;
 #pragma unroll
@@ -161,7 +165,11 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
                     const float g = fmaxf(fmaxf(bx[f] - q[f], q[f] - bx[DP + f]), 0.f);
                     lb = fmaf(g, g, lb);
                 }
-                if (__any(lb <= thr)) return t;
+                const unsigned long long reach = __ballot(lb <= thr);
+                if (reach) {
+                    const int rows = ((unsigned)reach ? 1 : 0) | ((reach >> 32) ? 2 : 0);
+                    return t | (rows << kRowShift);
+                }
                 ++skipped;
             }
             return -1;
@@ -174,7 +182,8 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
         const gfloat xg = (gfloat)xs_g;
         // The candidate's id bits come along, so that the exact recheck can
         // stage whole candidate rows from these registers.
-        auto load_b = [&](int t, float (&br)[2][KSTEPS + 2]) {
+        auto load_b = [&](int tv, float (&br)[2][KSTEPS + 2]) {
+            const int t = tv & kTileMask;
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
                 const gfloat rowc = xg + (int64_t)(t * kTile + 32 * cb + col) * DP + half;
@@ -190,9 +199,12 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
         // and its operands requested before the current tile is screened.
         // Two operand buffers, used alternately (no copies between them, so a
         // tile's loads are waited on only when that tile is screened).
-        auto process = [&](int t, float (&br)[2][KSTEPS + 2]) {
+        auto process = [&](int tv, float (&br)[2][KSTEPS + 2]) {
+            const int t = tv & kTileMask;
+            const int rows = tv >> kRowShift;
             ++scanned;
-            pairs += (long long)nq * min(kTile, n - t * kTile);
+            pairs += (long long)((rows & 1 ? min(nq, 32) : 0) + (rows & 2 ? max(0, nq - 32) : 0)) *
+                     min(kTile, n - t * kTile);
             const int cbase = t * kTile;
 
             // B operands in place: 0 in the pad slot of an odd d, then (1, h)
@@ -209,6 +221,7 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
             unsigned u_lo = 0, u_hi = 0;
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
+                if (!((rows >> rb) & 1)) continue;
                 f16v acc[2];
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
