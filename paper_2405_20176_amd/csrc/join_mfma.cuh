@@ -9,7 +9,8 @@
 // a dense contraction, computed by v_mfma_f32_32x32x2f32 in four 32 x 32
 // blocks over ceil(d / 2) + 1 K-steps: the coordinates, then one step whose
 // two K slots carry (-lim_i, 1) and (1, h_j).  A pair passes when its
-// accumulator is >= 0.  The rounding of that accumulation, with |lim_i|
+// accumulator is >= 0.  For odd d the coordinate steps' pad slot carries
+// (-lim_i, 1) instead and the test is accumulator >= -h_j.  The rounding of that accumulation, with |lim_i|
 // among the summed magnitudes, stays inside the prefilter's margin (the
 // margin also allows products and sums that round separately), so every
 // candidate the exact direct form would accept still passes.
@@ -55,7 +56,13 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
     using namespace mfma_detail;
     constexpr int DP = row_stride(D);
     constexpr int KS = KC > 0 ? KC : 1;
-    constexpr int KSTEPS = (D + 1) / 2;      // coordinate steps; one more carries -lim and h
+    constexpr int KSTEPS = (D + 1) / 2;      // coordinate steps
+    // Even d: one more step carries (-lim_i, 1) and (1, h_j), and a pair
+    // passes when its score is >= 0.  Odd d: the pad slot of the last
+    // coordinate step carries (-lim_i, 1), and h_j moves into the comparison
+    // (score >= -h_j, exact), which saves that step.
+    constexpr bool kFold = D % 2 == 1;
+    constexpr int NSTEP = kFold ? KSTEPS : KSTEPS + 1;
     constexpr float cq = (float)(2 * (8 * D + 24)) * 5.9604644775390625e-8f;
     __shared__ int s_unit, s_queue;
     __shared__ uint2 s_mask[64];            // per-query candidate masks of one tile pair
@@ -119,14 +126,17 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
 #pragma unroll
             for (int s = 0; s < KSTEPS; ++s) {
                 const float v = rowp[2 * s];
-                av[rb][s] = (D % 2 == 1 && s == KSTEPS - 1 && half) ? 0.f : v;
+                av[rb][s] = (kFold && s == KSTEPS - 1 && half) ? 0.f : v;
             }
         }
         auto refresh_limits = [&]() {
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
                 const float l = __shfl(lim, 32 * rb + col, 64);
-                av[rb][KSTEPS] = half ? 1.f : -l;
+                if (kFold)
+                    av[rb][KSTEPS - 1] = half ? -l : av[rb][KSTEPS - 1];
+                else
+                    av[rb][KSTEPS] = half ? 1.f : -l;
             }
         };
         refresh_limits();
@@ -211,9 +221,14 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
             // (the exact recheck reads only the coordinates and the id).
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                if (D % 2 == 1 && half) br[cb][KSTEPS - 1] = 0.f;
-                br[cb][KSTEPS] = half ? br[cb][KSTEPS] : 1.f;
+                if (kFold)
+                    br[cb][KSTEPS - 1] = half ? 1.f : br[cb][KSTEPS - 1];
+                else
+                    br[cb][KSTEPS] = half ? br[cb][KSTEPS] : 1.f;
             }
+            // Pass threshold of this lane's candidate column in each block.
+            const float nh0 = kFold ? -br[0][KSTEPS] : 0.f;
+            const float nh1 = kFold ? -br[1][KSTEPS] : 0.f;
             // One block row of queries at a time (32 accumulators live): the
             // scores, a screen (most tile pairs have no passing pair), then the
             // ballots, whose low and high halves lane 0 writes into the owning
@@ -227,19 +242,20 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
                 for (int cb = 0; cb < 2; ++cb) {
                     acc[cb] = f16v{};
 #pragma unroll
-                    for (int s2 = 0; s2 <= KSTEPS; ++s2)
+                    for (int s2 = 0; s2 < NSTEP; ++s2)
                         acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][s2], br[cb][s2], acc[cb], 0, 0, 0);
                 }
-                float mx = -INFINITY;       // NaN pads never pass
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) mx = fmaxf(mx, acc[cb][r]);
-                if (!__any(mx >= 0.f)) continue;
+                float mx0 = -INFINITY, mx1 = -INFINITY;     // NaN pads never pass
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const unsigned long long b0 = __ballot(acc[0][r] >= 0.f);
-                    const unsigned long long b1 = __ballot(acc[1][r] >= 0.f);
+                    mx0 = fmaxf(mx0, acc[0][r]);
+                    mx1 = fmaxf(mx1, acc[1][r]);
+                }
+                if (!__any(mx0 >= nh0 || mx1 >= nh1)) continue;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const unsigned long long b0 = __ballot(acc[0][r] >= nh0);
+                    const unsigned long long b1 = __ballot(acc[1][r] >= nh1);
                     if (b0 | b1) {
                         const int i0 = acc_row(rb, r, 0);
                         if (lane == 0) {
