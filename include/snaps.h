@@ -172,12 +172,23 @@ int snaps_knn_selfjoin(const snaps_population* P, uint32_t mask, int32_t k,
                        void* ws, size_t ws_bytes, void* stream);
 
 /* eps-range self-join (Sec. 3.5): for every object, the number of other
- * objects at Euclidean distance <= eps and their mean distance.
+ * objects at Euclidean distance <= eps and their mean distance, and
+ * optionally the pair list (the result set A without the self-pairs) in CSR
+ * form.
  *   count      [n] int32 device, output
- *   mean_dist  [n] float device, output (0 where count is 0), or NULL
- *   pair_off, pairs, pair_cap: the pair list is not produced by this
- *   version; pass NULL, NULL, 0 (anything else returns SNAPS_EUNSUPPORTED).
- * Returns SNAPS_EINVAL for eps <= 0 or non-finite, a bad mask or population. */
+ *   mean_dist  [n] float device, output (0 where count is 0)
+ *   pair_off   [n + 1] int64 device output, or NULL (no pair list):
+ *              pair_off[i] is where object i's row starts, pair_off[n] the
+ *              total number of pairs
+ *   pairs      [pair_cap] int32 device output, or NULL: row i holds the ids
+ *              of object i's neighbours in an unspecified order that repeats
+ *              from call to call; an entry whose position is >= pair_cap is
+ *              not written, so a caller compares pair_off[n] with pair_cap
+ *              (and may size pairs from a first call with pair_cap = 0)
+ * With a pair list the join runs twice (counts, then rows) and the workspace
+ * of snaps_workspace_bytes(SNAPS_OP_EPS, ...) is required even for small n.
+ * Returns SNAPS_EINVAL for eps <= 0 or non-finite, a bad mask or population,
+ * pair_cap < 0, or pairs / pair_cap > 0 without pair_off. */
 int snaps_eps_selfjoin(const snaps_population* P, uint32_t mask, float eps,
                        int32_t* count, float* mean_dist,
                        int64_t* pair_off, int32_t* pairs, int64_t pair_cap,

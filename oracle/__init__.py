@@ -15,6 +15,7 @@ from .snaps_oracle import (  # noqa: F401
     pair_distances,
     knn,
     eps_join,
+    eps_pairs,
     indegree,
     dense_rank,
     rank_keys,

@@ -111,6 +111,27 @@ def eps_join(X: np.ndarray, eps: float):
     return count, mean
 
 
+def eps_pairs(X: np.ndarray, eps: float) -> tuple[np.ndarray, np.ndarray]:
+    """The range self-join's result set (Sec. 3.5, the set A of Sec. 3.5.3
+    without the self-pairs) in CSR form: ``off`` int64 [n + 1] and ``ids``
+    int64, row i = the objects at distance <= eps from object i in
+    ascending id order."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    eps = float(eps)
+    rows = []
+    for b0 in range(0, n, _BLOCK):
+        b1 = min(n, b0 + _BLOCK)
+        D = pair_distances(X[b0:b1], X)
+        for r in range(b1 - b0):
+            hit = np.nonzero(D[r] <= eps)[0]
+            rows.append(hit[hit != b0 + r])
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    ids = np.concatenate(rows).astype(np.int64) if rows else np.zeros(0, dtype=np.int64)
+    return off, ids
+
+
 def indegree(ids: np.ndarray, n: int) -> np.ndarray:
     """In-degree of the kNN graph (Sec. 3.6.1): how many objects list each
     object among their k neighbours."""

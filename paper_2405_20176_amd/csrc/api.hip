@@ -364,6 +364,9 @@ struct RunJob {
     int32_t* knn_ids;
     float* knn_dist;
     float* knn_kth;
+    int64_t* pair_off;      // eps-only pair lists (snaps_eps_selfjoin)
+    int32_t* pairs;
+    int64_t pair_cap;
 };
 
 void count_large(const std::vector<RunJob>& jobs, int* n_large, int* n_lrank) {
@@ -433,6 +436,9 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         j.knn_ids = r.knn_ids;
         j.knn_dist = r.knn_dist;
         j.knn_kth = r.knn_kth;
+        j.pair_off = r.pair_off;
+        j.pairs = r.pairs;
+        j.pair_cap = r.pair_cap;
         table[i] = j;
         off += r.plan.bytes;
         total_tiles += r.plan.ntiles;
@@ -653,7 +659,8 @@ size_t snaps_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t k) {
     else if (k < 1 || k > n - 1 || k > kMaxK) return 0;
     if (op != SNAPS_OP_KNN && op != SNAPS_OP_EPS && op != SNAPS_OP_SCORES) return 0;
     const JobPlan p = plan_job(n, d, k, op == SNAPS_OP_SCORES);
-    return meta_layout(1, p.large ? 1 : 0, (p.large_rank && op == SNAPS_OP_SCORES) ? 1 : 0).bytes + p.bytes;
+    const size_t run = meta_layout(1, p.large ? 1 : 0, (p.large_rank && op == SNAPS_OP_SCORES) ? 1 : 0).bytes + p.bytes;
+    return op == SNAPS_OP_EPS ? align_up(run) + pair_scan_scratch(n) : run;
 }
 
 static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune, std::vector<RunJob>* out) {
@@ -721,9 +728,10 @@ int snaps_eps_selfjoin(const snaps_population* P, uint32_t mask, float eps, int3
     rc = check_eps(eps);
     if (rc != SNAPS_OK) return rc;
     if (!count) return fail(SNAPS_EINVAL, "count is NULL");
-    if (pair_off || pairs || pair_cap)
-        return fail(SNAPS_EUNSUPPORTED, "pair lists are not produced by this version");
     if (!mean_dist) return fail(SNAPS_EINVAL, "mean_dist is NULL");
+    if (pair_cap < 0) return fail(SNAPS_EINVAL, "pair_cap must be >= 0");
+    if ((pairs || pair_cap > 0) && !pair_off) return fail(SNAPS_EINVAL, "a pair list needs pair_off");
+    if (pair_cap > 0 && !pairs) return fail(SNAPS_EINVAL, "pair_cap > 0 needs pairs");
     RunJob r{};
     r.pop = P;
     r.mask = mask;
@@ -731,7 +739,28 @@ int snaps_eps_selfjoin(const snaps_population* P, uint32_t mask, float eps, int3
     r.plan = plan_job(P->n, popcount32(mask), 0, false);
     r.eps_count = count;
     r.eps_mean = mean_dist;
-    return run({r}, Tune{0, 0, 0, 0}, ws, ws_bytes, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!pair_off) return run({r}, Tune{0, 0, 0, 0}, ws, ws_bytes, s);
+    // Pair lists: counts, their prefix sums, then the same join again (one
+    // wavefront per query tile, so each query appends its own row), writing
+    // each hit at its row start plus the hits before it.
+    const size_t need_run = run_workspace({r});
+    const size_t scan_at = align_up(need_run);
+    const size_t need = scan_at + pair_scan_scratch(P->n);
+    if (!ws) return fail(SNAPS_EINVAL, "workspace is NULL (%zu bytes needed)", need);
+    if (ws_bytes < need) return fail(SNAPS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    Tune tn{};
+    tn.split = 1;
+    tn.mq = 1;
+    int rc2 = run({r}, tn, ws, ws_bytes, s);
+    if (rc2 != SNAPS_OK) return rc2;
+    hipError_t e = launch_pair_offsets(count, P->n, pair_off, static_cast<char*>(ws) + scan_at, s);
+    if (e != hipSuccess) return hip_fail(e, "pair offsets launch");
+    if (pair_cap == 0) return SNAPS_OK;
+    r.pair_off = pair_off;
+    r.pairs = pairs;
+    r.pair_cap = pair_cap;
+    return run({r}, tn, ws, ws_bytes, s);
 }
 
 int snaps_outlier_scores(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune, void* ws,

@@ -141,9 +141,25 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
         };
         refresh_limits();
 
+        // An eps-only job may also list each query's hits: the query's row of
+        // the pair list starts at pair_off[id]; hits are appended in the
+        // order the walk meets them (pad lanes write nothing).
+        int32_t* const prow = KC == 0 ? Jp->pairs : nullptr;
+        int64_t poff = 0, pcap = 0;
+        if (KC == 0 && prow && qpos < n) {
+            poff = Jp->pair_off[Jp->perm[qpos]];
+            pcap = Jp->pair_cap;
+        }
+
         // Exact re-evaluation of one candidate (same operations as k_join).
         auto take = [&](float dd, int cid) {
             if (dd <= eps2) {
+                if constexpr (KC == 0) {
+                    if (prow) {
+                        const int64_t at = poff + cnt;
+                        if (at < pcap) prow[at] = cid;
+                    }
+                }
                 cnt += 1;
                 sum += (double)__builtin_amdgcn_sqrtf(dd);   // hardware sqrt, <= 1 ulp
             }

@@ -54,6 +54,9 @@ struct DevJob {
     int32_t* knn_ids;        // [n][k] or null
     float* knn_dist;         // [n][k] or null
     float* knn_kth;          // [n] squared float32 distance of the k-th neighbour, or null
+    int64_t* pair_off;       // eps-only jobs: [n + 1] start of each object's row in pairs, or null
+    int32_t* pairs;          // eps-only jobs: neighbour ids, row by row (entries at >= pair_cap dropped)
+    int64_t pair_cap;
 };
 
 // Small per-call metadata that lives next to the job table in the workspace.
@@ -265,6 +268,10 @@ hipError_t launch_eps_sample(const EpsJob* jobs, const int32_t* prefix, int n_jo
 hipError_t launch_ensemble(const DevJob* table, int n_jobs, const int32_t* tile_prefix, int total_tiles,
                            hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t n, int32_t v, hipStream_t s);
+// off[0] = 0, off[i + 1] = off[i] + count[i] (int64), i < n; scratch holds
+// pair_scan_scratch(n) bytes.
+size_t pair_scan_scratch(int64_t n);
+hipError_t launch_pair_offsets(const int32_t* count, int64_t n, int64_t* off, void* scratch, hipStream_t s);
 hipError_t launch_serve_finish(const DevJob& j, const LargeIndex& li, float* rk2, float* tmax, uint32_t* tkey,
                                const float* kth, hipStream_t s);
 hipError_t launch_serve_super(int ntiles, int dp, const float* boxes, const float* tmax, float* sbox, float* smax,

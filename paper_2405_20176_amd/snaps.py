@@ -219,14 +219,33 @@ def snaps_knn_selfjoin(pop: Population, mask: int, k: int, ids: torch.Tensor, di
 
 
 def snaps_eps_selfjoin(pop: Population, mask: int, eps: float, count: torch.Tensor, mean_dist: torch.Tensor,
-                       ws: Optional[torch.Tensor] = None, stream=None):
+                       ws: Optional[torch.Tensor] = None, stream=None, pair_off: Optional[torch.Tensor] = None,
+                       pairs: Optional[torch.Tensor] = None):
+    """Range self-join; with ``pair_off`` ([n + 1] int64) also the CSR pair
+    list into ``pairs`` (int32, its length is the capacity)."""
     lib = load_library()
     d = bin(int(mask)).count("1")
     need = lib.snaps_workspace_bytes(OP_EPS, pop.n, d, 0)
     if ws is None:
         ws = _workspace(need, pop.cols.device)
+    cap = int(pairs.numel()) if pairs is not None else 0
     _check(lib.snaps_eps_selfjoin(ctypes.byref(pop.c), int(mask), float(eps), _ptr(count), _ptr(mean_dist),
-                                  None, None, 0, _ptr(ws), ws.numel(), _stream(stream)))
+                                  _ptr(pair_off), _ptr(pairs), cap, _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def snaps_eps_pairs(pop: Population, mask: int, eps: float, stream=None):
+    """Counts, mean distances and the complete pair list of one subspace:
+    a first call sizes the list, a second fills it.  Returns (count,
+    mean_dist, pair_off, pairs) as CUDA tensors."""
+    dev = pop.cols.device
+    count = torch.empty(pop.n, dtype=torch.int32, device=dev)
+    mean = torch.empty(pop.n, dtype=torch.float32, device=dev)
+    off = torch.empty(pop.n + 1, dtype=torch.int64, device=dev)
+    snaps_eps_selfjoin(pop, mask, eps, count, mean, stream=stream, pair_off=off)
+    total = int(off[-1].item())
+    pairs = torch.empty(max(total, 1), dtype=torch.int32, device=dev)
+    snaps_eps_selfjoin(pop, mask, eps, count, mean, stream=stream, pair_off=off, pairs=pairs)
+    return count, mean, off, pairs[:total]
 
 
 @dataclass

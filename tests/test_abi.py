@@ -81,8 +81,15 @@ def test_eps_validation(lib):
     c = ctypes.c_void_p(0x2000)
     for eps in (0.0, -1.0, float("inf"), float("nan")):
         assert lib.snaps_eps_selfjoin(ctypes.byref(p), 0b11, eps, c, c, None, None, 0, None, 0, None) == -1
-    # pair lists are not produced by this version
-    assert lib.snaps_eps_selfjoin(ctypes.byref(p), 0b11, 0.1, c, c, c, c, 10, None, 0, None) == -4
+    # pair list arguments: a capacity needs the list and its row starts;
+    # a negative capacity is rejected; a workspace is required (checked
+    # before any device work)
+    assert lib.snaps_eps_selfjoin(ctypes.byref(p), 0b11, 0.1, c, c, None, c, 10, None, 0, None) == -1
+    assert lib.snaps_eps_selfjoin(ctypes.byref(p), 0b11, 0.1, c, c, c, None, 10, None, 0, None) == -1
+    assert lib.snaps_eps_selfjoin(ctypes.byref(p), 0b11, 0.1, c, c, c, c, -1, None, 0, None) == -1
+    assert lib.snaps_eps_selfjoin(ctypes.byref(p), 0b11, 0.1, c, c, c, c, 10, None, 0, None) == -1
+    need = lib.snaps_workspace_bytes(1, 100, 2, 0)          # SNAPS_OP_EPS
+    assert lib.snaps_eps_selfjoin(ctypes.byref(p), 0b11, 0.1, c, c, c, c, 10, c, need - 1, None) == -2
 
 
 def test_population_validation(lib):

@@ -797,3 +797,62 @@ def test_eps_sampler_beyond_one_dispatch(S):
     out = S.snaps_eps_sample(specs)
     for i in (0, jobs - 1):
         assert torch.equal(S.snaps_eps_sample([specs[i]])[0], out[i]), i
+
+
+# ------------------------------------------------ eps pair lists (Sec. 3.5)
+
+def _check_pair_rows(P, eps, off, pairs, rows):
+    """Rows of the GPU pair list against the float64 oracle: equal as sets
+    unless an oracle distance of the row sits in the eps band; then every
+    neighbour strictly inside the band is listed and nothing outside it."""
+    D = O.pair_distances(P[rows], P)
+    for r, i in enumerate(rows):
+        got = np.sort(pairs[off[i]:off[i + 1]])
+        assert np.unique(got).size == got.size and i not in got, i
+        di = D[r].copy()
+        di[i] = np.inf
+        if (np.abs(di - eps) <= TAU * eps).any():
+            inner = np.nonzero(di < eps * (1 - TAU))[0]
+            outer = np.nonzero(di <= eps * (1 + TAU))[0]
+            assert set(inner.tolist()) <= set(got.tolist()) <= set(outer.tolist()), i
+        else:
+            np.testing.assert_array_equal(got, np.nonzero(di <= eps)[0])
+
+
+@pytest.mark.parametrize("n,d", [(1000, 3), (3000, 7), (40000, 4)])
+def test_eps_pair_list(S, n, d):
+    """The CSR pair list of snaps_eps_selfjoin: row starts are the prefix
+    sums of the counts, rows match the oracle's result set (band rule), the
+    counts and means equal the call without a list, and a capacity below the
+    total writes exactly the first entries of the full list and nothing past
+    the capacity.  n = 40,000 runs through the device-wide index."""
+    rng = np.random.default_rng(70 + d)
+    x = rng.random((n, 8)).astype(np.float32)
+    mask = (1 << d) - 1
+    P = O.project(x, mask).astype(np.float32)
+    sample = np.sort(rng.choice(n, size=64, replace=False))
+    eps = float(O.eps_from_sample(P, sample, 8.0))
+    pop = S.Population.from_rows(x)
+    count, mean, off, pairs = S.snaps_eps_pairs(pop, mask, eps)
+    count, mean = count.cpu().numpy(), mean.cpu().numpy()
+    off, pl = off.cpu().numpy(), pairs.cpu().numpy()
+    assert off[0] == 0 and (np.diff(off) == count).all() and off[-1] == pl.size
+    c0 = torch.empty(n, dtype=torch.int32, device="cuda")
+    m0 = torch.empty(n, dtype=torch.float32, device="cuda")
+    S.snaps_eps_selfjoin(pop, mask, eps, c0, m0)
+    np.testing.assert_array_equal(c0.cpu().numpy(), count)
+    np.testing.assert_array_equal(m0.cpu().numpy(), mean)
+    rows = np.arange(n) if n <= 3000 else np.sort(rng.choice(n, size=300, replace=False))
+    _check_pair_rows(P, eps, off, pl, rows)
+    if n <= 3000:                                   # the relation is symmetric outside the band
+        ro, rid = O.eps_pairs(P, eps)
+        assert abs(int(ro[-1]) - pl.size) <= 2 * int((np.abs(O.pair_distances(P, P) - eps) <= TAU * eps).sum())
+    # capacity below the total
+    cap = pl.size // 2
+    buf = torch.full((cap + 100,), -7, dtype=torch.int32, device="cuda")
+    off2 = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    S.snaps_eps_selfjoin(pop, mask, eps, c0, m0, pair_off=off2, pairs=buf[:cap])
+    b = buf.cpu().numpy()
+    np.testing.assert_array_equal(off2.cpu().numpy(), off)
+    np.testing.assert_array_equal(b[:cap], pl[:cap])
+    assert (b[cap:] == -7).all()

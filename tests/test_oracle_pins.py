@@ -511,3 +511,20 @@ def test_grid_selection_by_hand():
     np.testing.assert_allclose(sel["similarity"][1, 0], [1.0, 0.5, 0.5])
     np.testing.assert_allclose(sel["similarity"][1, 1], [0.5, 0.0, 1.0])
     assert int(sel["select"][1]) == 0
+
+
+def test_eps_pairs_against_scipy_ball_query():
+    """The pair list of the range join equals scipy's ball query (closed
+    ball, self removed, ids ascending) row by row, and its row lengths are
+    the join's counts."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(35)
+    x = rng.random((300, 3))
+    eps = 0.12
+    off, ids = O.eps_pairs(x, eps)
+    balls = cKDTree(x).query_ball_point(x, eps)
+    for i in range(300):
+        ref = sorted(j for j in balls[i] if j != i)
+        assert ids[off[i]:off[i + 1]].tolist() == ref
+    c, _ = O.eps_join(x, eps)
+    np.testing.assert_array_equal(np.diff(off), c)
