@@ -318,6 +318,9 @@ def main():
                     help="skip timing the sampled eps_min / eps_max radii of every subspace")
     ap.add_argument("--no-eps-grid", dest="eps_grid", action="store_false",
                     help="skip timing the eps-grid selection on a slice of the subspaces")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="use the library's fixed per-d defaults instead of the measured per-class walk")
+    ap.add_argument("--autotune-sample", type=int, default=64, help="jobs timed per class by the autotuner")
     ap.add_argument("--no-k-grid", dest="k_grid", action="store_false",
                     help="skip timing the k-grid selection on a slice of the subspaces")
     ap.add_argument("--grid-spaces", type=int, default=1024,
@@ -375,6 +378,26 @@ def main():
                            out_kmean[i].data_ptr())
         j.rank = out_rank[i].data_ptr()
         j.ensemble = out_ens[i].data_ptr()
+    # Per-class choice of the candidate walk (box pruning and its indexed
+    # dimensions, or brute force), measured on a sample of each class's jobs
+    # before anything is timed.
+    tuned = None
+    if a.autotune:
+        from types import SimpleNamespace
+        from paper_2405_20176_amd import autotune as AT
+        t_at = time.perf_counter()
+        specs = [SimpleNamespace(pop=pop, mask=int(masks[i]), k=k, eps=float(eps_tab[i]), mode=0, index_dims=0)
+                 for i in range(n_sp)]
+        table = AT.tune(specs, sample=a.autotune_sample)
+        AT.apply(specs, table)
+        for i in range(n_sp):
+            jobs[i].mode, jobs[i].index_dims = specs[i].mode, specs[i].index_dims
+        tuned = {"seconds": time.perf_counter() - t_at, "sample_per_class": a.autotune_sample,
+                 "choice": {key: [v["mode"], v["index_dims"]] for key, v in table.items()},
+                 "note": "mode 1 = every candidate tile, 2 = box pruning on index_dims indexed dimensions; "
+                         "measured per (d, log2 n) class on sampled jobs, outside the timed region"}
+        log(f"autotune: {len(table)} classes in {tuned['seconds']:.1f} s: "
+            + ", ".join(f"{key}={v['mode']}/{v['index_dims']}" for key, v in table.items()))
     chunk = a.chunk if a.chunk > 0 else n_sp
     chunks = [(s, min(n_sp, s + chunk)) for s in range(0, n_sp, chunk)]
     job_ptr = lambda s: ctypes.cast(ctypes.byref(jobs, s * ctypes.sizeof(S.c_job)), ctypes.POINTER(S.c_job))
@@ -474,6 +497,7 @@ def main():
                  "candidates_per_result": pairs / a.steps / results_per_step,
                  "tiles_scanned": scanned / a.steps, "tiles_skipped": skipped / a.steps,
                  "evals_per_s": pairs / (join_ms / 1000.0)},
+        "autotune": tuned,
     }
 
     if not a.no_plain:

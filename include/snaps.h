@@ -97,6 +97,10 @@ typedef struct {
     float* ensemble;        /* [n] device or NULL (needs rank): the mean of the object's four
                                ranks, the average over the four methods that Sec. 5 suggests
                                for objects outlying in several of them; lower = more outlying */
+    int32_t mode;           /* 0: the call's snaps_tuning.mode; else this job's (1 brute force,
+                               2 box pruning) -- per-job choices such as an autotuner's */
+    int32_t index_dims;     /* 0: the call's snaps_tuning.index_dims; else this job's, 1..6
+                               (capped at d) */
 } snaps_job;
 
 /* Passes of snaps_outlier_scores (snaps_tuning.passes). */

@@ -367,6 +367,8 @@ struct RunJob {
     int64_t* pair_off;      // eps-only pair lists (snaps_eps_selfjoin)
     int32_t* pairs;
     int64_t pair_cap;
+    int32_t mode;           // per-job overrides of the call's tuning (0: none)
+    int32_t index_dims;
 };
 
 void count_large(const std::vector<RunJob>& jobs, int* n_large, int* n_lrank) {
@@ -426,7 +428,10 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
     for (int i = 0; i < n_jobs; ++i) {
         const RunJob& r = jobs[i];
         job_base[i] = base + off;
-        DevJob j = make_devjob(r.pop, r.mask, r.plan, r.eps, tn, base + off);
+        Tune tj = tn;
+        if (r.mode > 0) tj.mode = r.mode;
+        if (r.index_dims > 0) tj.index_dims = r.index_dims;
+        DevJob j = make_devjob(r.pop, r.mask, r.plan, r.eps, tj, base + off);
         j.eps_count = r.eps_count;
         j.eps_mean = r.eps_mean;
         j.indeg = r.indeg;
@@ -691,6 +696,11 @@ static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, const snaps_tunin
         r.rank = j.rank;
         if (j.ensemble && !j.rank) return fail(SNAPS_EINVAL, "job %d: the ensemble output needs the rank output", i);
         r.ensemble = j.ensemble;
+        if (j.mode < 0 || j.mode > 2) return fail(SNAPS_EINVAL, "job %d: mode must be 0, 1 or 2", i);
+        if (j.index_dims < 0 || j.index_dims > kMaxIndexDims)
+            return fail(SNAPS_EINVAL, "job %d: index_dims must be in [0, %d]", i, kMaxIndexDims);
+        r.mode = j.mode;
+        r.index_dims = j.index_dims;
         out->push_back(r);
     }
     return SNAPS_OK;

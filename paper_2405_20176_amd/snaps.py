@@ -46,7 +46,7 @@ class c_scores(ctypes.Structure):
 class c_job(ctypes.Structure):
     _fields_ = [("pop", ctypes.POINTER(c_population)), ("mask", ctypes.c_uint32), ("k", ctypes.c_int32),
                 ("eps", ctypes.c_float), ("out", c_scores), ("rank", ctypes.c_void_p),
-                ("ensemble", ctypes.c_void_p)]
+                ("ensemble", ctypes.c_void_p), ("mode", ctypes.c_int32), ("index_dims", ctypes.c_int32)]
 
 
 class c_tuning(ctypes.Structure):
@@ -261,6 +261,8 @@ class Job:
     knn_mean: torch.Tensor
     rank: Optional[torch.Tensor] = None      # [4, n] int32
     ensemble: Optional[torch.Tensor] = None  # [n] float32, mean of the four ranks
+    mode: int = 0                            # per-job overrides of the call's tuning (0: none)
+    index_dims: int = 0
 
     @classmethod
     def alloc(cls, pop: Population, mask: int, k: int, eps: float, with_rank: bool = True,
@@ -285,6 +287,8 @@ def _c_jobs(jobs: Sequence[Job]):
                               j.knn_mean.data_ptr())
         arr[i].rank = None if j.rank is None else j.rank.data_ptr()
         arr[i].ensemble = None if j.ensemble is None else j.ensemble.data_ptr()
+        arr[i].mode = j.mode
+        arr[i].index_dims = j.index_dims
     return arr
 
 

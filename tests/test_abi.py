@@ -121,6 +121,15 @@ def test_outlier_scores_validation(lib):
         t = c_tuning()
         setattr(t, field, value)
         assert lib.snaps_outlier_scores(ctypes.byref(job), 1, ctypes.byref(t), None, 0, None) == -1, field
+    # per-job overrides of the walk: mode 0..2, index_dims 0..6
+    for field, value in (("mode", 3), ("mode", -1), ("index_dims", 7), ("index_dims", -1)):
+        bj = c_job.from_buffer_copy(job)
+        setattr(bj, field, value)
+        assert lib.snaps_outlier_scores(ctypes.byref(bj), 1, None, None, 0, None) == -1, (field, value)
+        assert lib.snaps_outlier_scores_workspace(ctypes.byref(bj), 1, None) == 0, (field, value)
+    okj = c_job.from_buffer_copy(job)
+    okj.mode, okj.index_dims = 2, 3
+    assert lib.snaps_outlier_scores_workspace(ctypes.byref(okj), 1, None) > 0
     # an ensemble output needs the rank output
     ej = c_job.from_buffer_copy(job)
     ej.ensemble = 0x50

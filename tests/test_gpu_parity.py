@@ -856,3 +856,50 @@ def test_eps_pair_list(S, n, d):
     np.testing.assert_array_equal(off2.cpu().numpy(), off)
     np.testing.assert_array_equal(b[:cap], pl[:cap])
     assert (b[cap:] == -7).all()
+
+
+# ------------------------------------- per-job walk settings and the autotuner
+
+def test_per_job_walk_settings_and_autotuner(S):
+    """Per-job mode / index_dims (brute force, or box pruning on 2..6
+    indexed dimensions) change only the time: counts, in-degrees and kNN
+    means are identical, eps means agree to the summation order.  The
+    autotuner times every candidate setting of each class and its choices,
+    applied, keep the results."""
+    from paper_2405_20176_amd import autotune as AT
+    rng = np.random.default_rng(91)
+    x = rng.random((5000, 15)).astype(np.float32)
+    pop = S.Population.from_rows(x)
+    masks = [0b111, 0b1111111, 0b111111111111]
+    epss = [0.08 * math.sqrt(bin(m).count("1")) for m in masks]
+
+    def run(settings, jobs=None):
+        jobs = jobs or [S.Job.alloc(pop, m, 10, e) for m, e in zip(masks, epss)]
+        for j, (mo, c) in zip(jobs, settings):
+            j.mode, j.index_dims = mo, c
+        S.snaps_outlier_scores(jobs, S.tuning(split=1))
+        torch.cuda.synchronize()
+        return [{key: getattr(j, key).cpu().numpy() for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank")}
+                for j in jobs]
+
+    def same(a, b, label):
+        for ra, rb in zip(a, b):
+            for key in ("eps_count", "indeg", "knn_mean"):
+                np.testing.assert_array_equal(ra[key], rb[key], err_msg=f"{key} {label}")
+            np.testing.assert_allclose(ra["eps_mean"], rb["eps_mean"], rtol=TAU, err_msg=label)
+            for t in (0, 2, 3):
+                np.testing.assert_array_equal(ra["rank"][t], rb["rank"][t], err_msg=f"rank {t} {label}")
+
+    ref = run([(0, 0)] * 3)
+    check_scores(ref[1], run_oracle(x, masks[1], 10, epss[1]), 10, epss[1], label="defaults d=7")
+    for setting in [(1, 0), (2, 2), (2, 3), (2, 6)]:
+        same(ref, run([setting] * 3), f"setting {setting}")
+    jobs = [S.Job.alloc(pop, m, 10, e) for m, e in zip(masks, epss)]
+    table = AT.tune(jobs, sample=2, reps=1)
+    assert set(table) == {AT.class_key(AT.job_class(j)) for j in jobs}
+    for key, v in table.items():
+        d = int(key[1:key.index("_")])
+        assert (v["mode"], v["index_dims"]) in AT.candidates(d)
+        assert set(v["ms"]) == {f"{m},{c}" for m, c in AT.candidates(d)}
+    assert AT.apply(jobs, table) == 3
+    same(ref, run([(j.mode, j.index_dims) for j in jobs], jobs), "autotuned")
