@@ -321,6 +321,9 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the library's fixed per-d defaults instead of the measured per-class walk")
     ap.add_argument("--autotune-sample", type=int, default=64, help="jobs timed per class by the autotuner")
+    ap.add_argument("--autotune-cache", default="", metavar="FILE",
+                    help="take the autotuner's table for this device from FILE if it holds one, else measure "
+                         "and store it there (profiling runs use it to keep the tuning launches out)")
     ap.add_argument("--no-k-grid", dest="k_grid", action="store_false",
                     help="skip timing the k-grid selection on a slice of the subspaces")
     ap.add_argument("--grid-spaces", type=int, default=1024,
@@ -388,11 +391,17 @@ def main():
         t_at = time.perf_counter()
         specs = [SimpleNamespace(pop=pop, mask=int(masks[i]), k=k, eps=float(eps_tab[i]), mode=0, index_dims=0)
                  for i in range(n_sp)]
-        table = AT.tune(specs, sample=a.autotune_sample)
+        devname = AT.device_key(dev)
+        table = AT.load(a.autotune_cache, devname) if a.autotune_cache else None
+        source = "cache" if table else "measured"
+        if not table:
+            table = AT.tune(specs, sample=a.autotune_sample)
+            if a.autotune_cache:
+                AT.save(a.autotune_cache, devname, table)
         AT.apply(specs, table)
         for i in range(n_sp):
             jobs[i].mode, jobs[i].index_dims = specs[i].mode, specs[i].index_dims
-        tuned = {"seconds": time.perf_counter() - t_at, "sample_per_class": a.autotune_sample,
+        tuned = {"seconds": time.perf_counter() - t_at, "source": source, "sample_per_class": a.autotune_sample,
                  "choice": {key: [v["mode"], v["index_dims"]] for key, v in table.items()},
                  "note": "mode 1 = every candidate tile, 2 = box pruning on index_dims indexed dimensions; "
                          "measured per (d, log2 n) class on sampled jobs, outside the timed region"}
