@@ -95,7 +95,11 @@ def apply(jobs: Iterable[S.Job], table: Dict[str, dict]) -> int:
 
 
 def device_key(device=None) -> str:
-    return torch.cuda.get_device_name(device)
+    """Cache key of a device: its architecture and compute-unit count (the
+    marketing name is not always available)."""
+    props = torch.cuda.get_device_properties(device)
+    arch = getattr(props, "gcnArchName", "") or props.name
+    return f"{arch} {props.multi_processor_count}cu"
 
 
 def load(path: str, device: str) -> Optional[Dict[str, dict]]:
