@@ -9,7 +9,7 @@ population size and on the data, so it is measured: for each class of jobs
 (d, floor(log2 n)) in a job list, a sample of its jobs runs the index and join
 passes under every candidate setting, and the fastest setting is kept.  The
 choices go into the jobs' per-job ``mode`` / ``index_dims`` and can be cached
-per device name in a JSON file.  Every setting gives the same results (the
+per device (architecture and compute units) in a JSON file.  Every setting gives the same results (the
 pruning is exact); only the time differs.
 """
 from __future__ import annotations
