@@ -333,7 +333,7 @@ def main():
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (each GPU box has one); run with --gpus 1",
+        print("bench.py: the path is measured on one GPU only (no multi-GPU form is built); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
