@@ -110,10 +110,11 @@ typedef struct {
 
 /* Optional tuning (NULL or zero fields = automatic). */
 typedef struct {
-    int32_t mode;           /* 0 auto, 1 brute force over every candidate tile,
-                               2 skip candidate tiles whose bounding box is provably out of reach */
+    int32_t mode;           /* 0 auto (2 up to d = 14, else 1), 1 brute force over every candidate
+                               tile, 2 skip candidate tiles whose bounding box is provably out of reach */
     int32_t split;          /* 0 auto, else waves sharing one query tile: 1, 2, 4 or 8 */
-    int32_t index_dims;     /* 0 auto (min(d, 6), as Sec. 3.8.1), else 1..min(d, 6) */
+    int32_t index_dims;     /* 0 auto (min(d, 4): the autotuner's usual choice; Sec. 3.8.1 uses
+                               min(d, 6), which serving states keep), else 1..min(d, 6) */
     int32_t filter;         /* 0 auto (3), 1 direct distance form only,
                                2 expanded-form prefilter on the vector ALU with exact direct
                                recheck, 3 the same prefilter as a dense contraction on the

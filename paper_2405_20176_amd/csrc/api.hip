@@ -43,6 +43,13 @@ constexpr size_t kAlign = 256;
 constexpr int64_t kMaxN = int64_t(1) << 30;   // objects per job (ids and tile counts stay in int32)
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Defaults of the walk when neither the call nor the job sets them: box
+// pruning up to d = 14 on min(d, 4) indexed dimensions (what the autotuner
+// picks for most classes of the SNAPShot1-shaped run; fewer dimensions cut
+// each one finer), brute force above.  Serving states keep min(d, 6).
+constexpr int kDefaultIndexDims = 4;
+constexpr int kDefaultPruneMaxD = 14;
+
 int popcount32(uint32_t m) { return __builtin_popcount(m); }
 
 int ceil_log2(int64_t v) {
@@ -248,7 +255,7 @@ DevJob make_devjob(const snaps_population* P, uint32_t mask, const JobPlan& p, f
     j.k = p.k;
     j.ntiles = p.ntiles;
     j.eps2 = eps > 0.f ? (float)((double)eps * (double)eps) : -1.f;
-    int c = tn.index_dims > 0 ? std::min(tn.index_dims, p.d) : std::min(p.d, kMaxIndexDims);
+    int c = tn.index_dims > 0 ? std::min(tn.index_dims, p.d) : std::min(p.d, kDefaultIndexDims);
     j.c = c;
     int f = 0;
     for (int b = 0; b < 32; ++b)
@@ -264,7 +271,7 @@ DevJob make_devjob(const snaps_population* P, uint32_t mask, const JobPlan& p, f
     j.flags = (p.large ? kJobRadixIndex : 0) | (p.large_rank ? kJobRadixRank : 0);
     if (tn.mode == 1) j.prune = 0;
     else if (tn.mode == 2) j.prune = 1;
-    else j.prune = p.d <= 10 ? 1 : 0;
+    else j.prune = p.d <= kDefaultPruneMaxD ? 1 : 0;
     j.xs = reinterpret_cast<float*>(ws_base + p.xs_off);
     j.perm = reinterpret_cast<int32_t*>(ws_base + p.perm_off);
     j.boxes = reinterpret_cast<float*>(ws_base + p.box_off);
@@ -989,7 +996,12 @@ int snaps_serve_state_build(const snaps_population* P, uint32_t mask, int32_t k,
     r.knn_mean = reinterpret_cast<float*>(base + L.kmean);
     r.knn_kth = reinterpret_cast<float*>(base + L.kth);
     r.rank = reinterpret_cast<int32_t*>(base + L.rank);
-    rc = run({r}, Tune{}, base + L.ws, L.ws_bytes, s);
+    // A serving state indexes min(d, 6) dimensions: single alerts are culled
+    // tile by tile, which the finer cut in more dimensions helps (measured:
+    // the batched default of 4 made p50 and p99 latency worse).
+    Tune ts{};
+    ts.index_dims = kMaxIndexDims;
+    rc = run({r}, ts, base + L.ws, L.ws_bytes, s);
     if (rc != SNAPS_OK) return rc;
     // Same addresses as run() chose for this single large job.
     char* wsb = base + L.ws;
@@ -997,7 +1009,7 @@ int snaps_serve_state_build(const snaps_population* P, uint32_t mask, int32_t k,
     char* jb = wsb + ml.bytes;
     const JobPlan& p = L.plan;
     const size_t rows = (size_t)p.ntiles * kTile;
-    DevJob j = make_devjob(P, mask, p, eps, Tune{}, jb);
+    DevJob j = make_devjob(P, mask, p, eps, ts, jb);
     LargeIndex li{};
     li.sel_col = reinterpret_cast<int32_t*>(jb + p.sel_off);
     li.sel_lo = reinterpret_cast<float*>(jb + p.sel_off) + kMaxIndexDims;
