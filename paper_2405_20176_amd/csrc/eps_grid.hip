@@ -55,9 +55,14 @@ __global__ __launch_bounds__(64) void k_grid_join(const GridJob* jobs, const int
     float q[D];
 #pragma unroll
     for (int f = 0; f < D; ++f) q[f] = J.cols[(int64_t)J.feat[f] * J.ld + qi];
-    float e2[kMaxGrid];                                   // uniform: held in scalar registers
+    // The radii (padded with the largest) in vector registers: compares
+    // with a scalar-register operand issue at a lower rate.
+    float e2[kMaxGrid];
 #pragma unroll
-    for (int r = 0; r < kMaxGrid; ++r) e2[r] = J.e2[r];
+    for (int r = 0; r < kMaxGrid; ++r) {
+        e2[r] = J.e2[r];
+        asm volatile("" : "+v"(e2[r]));
+    }
     const float emax2 = J.e2[g - 1];
     typedef float f4 __attribute__((ext_vector_type(4)));
     for (int c0 = 0; c0 < n; c0 += 4) {
@@ -76,7 +81,7 @@ __global__ __launch_bounds__(64) void k_grid_join(const GridJob* jobs, const int
             if (dd <= emax2 && c < n && c != qi && valid) {
                 int j = 0;                                 // the smallest radius that holds it
 #pragma unroll
-                for (int r = 0; r < kMaxGrid - 1; ++r) j += (r < g - 1 && dd > e2[r]) ? 1 : 0;
+                for (int r = 0; r < kMaxGrid - 1; ++r) j += dd > e2[r] ? 1 : 0;   // padded: never past g - 1
                 cnt[j][lane] += 1u;
                 sm[j][lane] += (double)__builtin_amdgcn_sqrtf(dd);   // hardware sqrt, <= 1 ulp
             }
