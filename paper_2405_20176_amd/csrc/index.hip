@@ -121,7 +121,13 @@ __global__ __launch_bounds__(64) void k_reorder(Meta m, int32_t n_jobs) {
     const int d = J.d;
     const int dp = row_stride(d);
     const bool valid = pos < n;
-    float* row = J.xs + (int64_t)pos * dp;
+    // The tile's 64 rows are one contiguous span of xs.  Each lane builds its
+    // row in LDS and the wave then stores the span with consecutive lanes on
+    // consecutive words: stored straight from the lanes, every store would
+    // touch 64 cache lines at a stride of dp words, and the partial-line
+    // writes cost several times the row bytes in HBM writes.
+    __shared__ float s_tile[kTile * row_stride(kMaxD)];
+    float* row = s_tile + lane * dp;
     float* box = J.boxes + (int64_t)t * 2 * dp;
     int id = INT32_MAX;
     if (valid) id = J.perm[pos];
@@ -152,6 +158,9 @@ __global__ __launch_bounds__(64) void k_reorder(Meta m, int32_t n_jobs) {
     row[d] = valid ? -0.5f * (norm * (1.0f - c0)) : qnan;
     // Slot d + 1: the object id, so the join reads it with the coordinates.
     row[d + 1] = __int_as_float(id);
+    __syncthreads();
+    float* span = J.xs + (int64_t)t * kTile * dp;
+    for (int i = lane; i < kTile * dp; i += kTile) span[i] = s_tile[i];
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t n, int32_t v) {
