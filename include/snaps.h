@@ -101,6 +101,10 @@ typedef struct {
                                2 box pruning) -- per-job choices such as an autotuner's */
     int32_t index_dims;     /* 0: the call's snaps_tuning.index_dims; else this job's, 1..6
                                (capped at d) */
+    int32_t* knn_ids;       /* [n][k] device or NULL: each object's k neighbours (Sec. 3.6,
+                               Fig. 1b) in ascending (distance, id) order -- the lists the
+                               in-degree of this call was counted from */
+    float* knn_dist;        /* [n][k] device or NULL: their Euclidean distances */
 } snaps_job;
 
 /* Passes of snaps_outlier_scores (snaps_tuning.passes). */

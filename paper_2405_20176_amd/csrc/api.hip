@@ -621,6 +621,8 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         if (e != hipSuccess) return hip_fail(e, "reorder launch");
     }
     if (do_join) {
+        e = launch_zero_indeg(meta, n_jobs, (int32_t)total_tiles, s);
+        if (e != hipSuccess) return hip_fail(e, "in-degree reset launch");
         rc = launch_joins(meta, plans, tn, mq, di.cus, s);
         if (rc != SNAPS_OK) return rc;
     }
@@ -708,6 +710,9 @@ static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, const snaps_tunin
             return fail(SNAPS_EINVAL, "job %d: index_dims must be in [0, %d]", i, kMaxIndexDims);
         r.mode = j.mode;
         r.index_dims = j.index_dims;
+        if (j.knn_dist && !j.knn_ids) return fail(SNAPS_EINVAL, "job %d: knn_dist needs knn_ids", i);
+        r.knn_ids = j.knn_ids;
+        r.knn_dist = j.knn_dist;
         out->push_back(r);
     }
     return SNAPS_OK;

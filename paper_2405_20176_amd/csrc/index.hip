@@ -132,7 +132,6 @@ __global__ __launch_bounds__(64) void k_reorder(Meta m, int32_t n_jobs) {
     int id = INT32_MAX;
     if (valid) id = J.perm[pos];
     else J.perm[pos] = INT32_MAX;
-    if (valid && J.indeg) J.indeg[pos] = 0;
     const float qnan = __int_as_float(0x7fc00000);
     float norm = 0.f;
 #pragma unroll
@@ -161,6 +160,28 @@ __global__ __launch_bounds__(64) void k_reorder(Meta m, int32_t n_jobs) {
     __syncthreads();
     float* span = J.xs + (int64_t)t * kTile * dp;
     for (int i = lane; i < kTile * dp; i += kTile) span[i] = s_tile[i];
+}
+
+// Clears the in-degree outputs of every job (four 64-object tiles per
+// workgroup) at the start of the join pass, which adds to them atomically:
+// a replay of the join pass alone recomputes the same in-degrees.
+__global__ __launch_bounds__(256) void k_zero_indeg(Meta m, int32_t n_jobs, int32_t total_tiles) {
+    const int u = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (u >= total_tiles) return;
+    int lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (m.tile_prefix[mid] <= u) lo = mid; else hi = mid;
+    }
+    int32_t* indeg = m.table[lo].indeg;
+    const int64_t i = (int64_t)(u - m.tile_prefix[lo]) * kTile + (threadIdx.x & 63);
+    if (indeg && i < m.table[lo].n) indeg[i] = 0;
+}
+
+hipError_t launch_zero_indeg(const Meta& m, int32_t n_jobs, int32_t total_tiles, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_indeg, dim3((total_tiles + 3) / 4), dim3(256), 0, s, m, n_jobs, total_tiles);
+    return hipGetLastError();
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t n, int32_t v) {

@@ -268,6 +268,8 @@ hipError_t launch_eps_sample(const EpsJob* jobs, const int32_t* prefix, int n_jo
 hipError_t launch_ensemble(const DevJob* table, int n_jobs, const int32_t* tile_prefix, int total_tiles,
                            hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t n, int32_t v, hipStream_t s);
+// Zero the in-degree output of every job of a call (start of the join pass).
+hipError_t launch_zero_indeg(const Meta& m, int32_t n_jobs, int32_t total_tiles, hipStream_t s);
 // off[0] = 0, off[i + 1] = off[i] + count[i] (int64), i < n; scratch holds
 // pair_scan_scratch(n) bytes.
 size_t pair_scan_scratch(int64_t n);

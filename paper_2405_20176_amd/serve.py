@@ -90,6 +90,8 @@ class Batcher:
         self.waiting: Deque[Request] = collections.deque()
         self.inflight: List[Tuple[object, List[Request], int]] = []
         self.finished: List[Request] = []
+        self.max_inflight = 0          # most batches on the device at once
+        self.batches_launched = 0
 
     def submit(self, r: Request):
         if self.adm.never_fits(r.device_bytes()):
@@ -121,6 +123,8 @@ class Batcher:
             r.admitted = now
             r.status = "running"
         self.inflight.append((self.ex.launch(batch), batch, nbytes))
+        self.batches_launched += 1
+        self.max_inflight = max(self.max_inflight, len(self.inflight))
         return True
 
     def _reap(self) -> bool:

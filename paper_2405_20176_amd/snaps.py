@@ -46,7 +46,8 @@ class c_scores(ctypes.Structure):
 class c_job(ctypes.Structure):
     _fields_ = [("pop", ctypes.POINTER(c_population)), ("mask", ctypes.c_uint32), ("k", ctypes.c_int32),
                 ("eps", ctypes.c_float), ("out", c_scores), ("rank", ctypes.c_void_p),
-                ("ensemble", ctypes.c_void_p), ("mode", ctypes.c_int32), ("index_dims", ctypes.c_int32)]
+                ("ensemble", ctypes.c_void_p), ("mode", ctypes.c_int32), ("index_dims", ctypes.c_int32),
+                ("knn_ids", ctypes.c_void_p), ("knn_dist", ctypes.c_void_p)]
 
 
 class c_tuning(ctypes.Structure):
@@ -263,17 +264,21 @@ class Job:
     ensemble: Optional[torch.Tensor] = None  # [n] float32, mean of the four ranks
     mode: int = 0                            # per-job overrides of the call's tuning (0: none)
     index_dims: int = 0
+    knn_ids: Optional[torch.Tensor] = None   # [n, k] int32, the kNN lists the in-degree was counted from
+    knn_dist: Optional[torch.Tensor] = None  # [n, k] float32
 
     @classmethod
     def alloc(cls, pop: Population, mask: int, k: int, eps: float, with_rank: bool = True,
-              with_ensemble: bool = False) -> "Job":
+              with_ensemble: bool = False, with_lists: bool = False) -> "Job":
         dev = pop.cols.device
         n = pop.n
         return cls(pop, int(mask), int(k), float(eps),
                    torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
                    torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
                    torch.empty((4, n), dtype=torch.int32, device=dev) if with_rank else None,
-                   torch.empty(n, dtype=torch.float32, device=dev) if (with_rank and with_ensemble) else None)
+                   torch.empty(n, dtype=torch.float32, device=dev) if (with_rank and with_ensemble) else None,
+                   knn_ids=torch.empty((n, k), dtype=torch.int32, device=dev) if with_lists else None,
+                   knn_dist=torch.empty((n, k), dtype=torch.float32, device=dev) if with_lists else None)
 
 
 def _c_jobs(jobs: Sequence[Job]):
@@ -289,6 +294,8 @@ def _c_jobs(jobs: Sequence[Job]):
         arr[i].ensemble = None if j.ensemble is None else j.ensemble.data_ptr()
         arr[i].mode = j.mode
         arr[i].index_dims = j.index_dims
+        arr[i].knn_ids = None if j.knn_ids is None else j.knn_ids.data_ptr()
+        arr[i].knn_dist = None if j.knn_dist is None else j.knn_dist.data_ptr()
     return arr
 
 
@@ -342,6 +349,120 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class JobTable:
+    """Many jobs in one job table over resident outputs: the outputs of every
+    job live in flat device buffers (job i at offset off[i], [4][n] ranks at
+    4 off[i], lists at off_k[i]), so thousands of jobs cost one allocation
+    per output.  ``specs``: sequence of (Population, mask, k, eps).  Per-job
+    walk settings (``mode``, ``index_dims``) can be set before plans are
+    built; ``plans`` captures the three passes of the whole table as graphs
+    over one workspace."""
+
+    def __init__(self, specs, with_rank: bool = True, with_ensemble: bool = False, with_lists: bool = False,
+                 device=None):
+        self.specs = [(p, int(m), int(k), float(e)) for p, m, k, e in specs]
+        nj = len(self.specs)
+        if nj == 0:
+            raise ValueError("no jobs")
+        dev = device or self.specs[0][0].cols.device
+        ns = [p.n for p, _, _, _ in self.specs]
+        self.off = [0]
+        self.off_k = [0]
+        for (p, _, k, _), n in zip(self.specs, ns):
+            self.off.append(self.off[-1] + n)
+            self.off_k.append(self.off_k[-1] + n * k)
+        total, total_k = self.off[-1], self.off_k[-1]
+        self.eps_count = torch.empty(total, dtype=torch.int32, device=dev)
+        self.eps_mean = torch.empty(total, dtype=torch.float32, device=dev)
+        self.indeg = torch.empty(total, dtype=torch.int32, device=dev)
+        self.knn_mean = torch.empty(total, dtype=torch.float32, device=dev)
+        self.rank = torch.empty(4 * total, dtype=torch.int32, device=dev) if with_rank else None
+        self.ensemble = torch.empty(total, dtype=torch.float32, device=dev) if (with_rank and with_ensemble) else None
+        self.knn_ids = torch.empty(total_k, dtype=torch.int32, device=dev) if with_lists else None
+        self.knn_dist = torch.empty(total_k, dtype=torch.float32, device=dev) if with_lists else None
+        self.mode = [0] * nj
+        self.index_dims = [0] * nj
+        self.arr = (c_job * nj)()
+        self._pops = {}
+        for i, (pop, mask, k, eps) in enumerate(self.specs):
+            key = id(pop)
+            if key not in self._pops:
+                self._pops[key] = (pop, ctypes.pointer(pop.c))
+            j = self.arr[i]
+            j.pop = self._pops[key][1]
+            j.mask, j.k, j.eps = mask, k, eps
+            o = self.off[i]
+            j.out = c_scores(self._at(self.eps_count, o), self._at(self.eps_mean, o), self._at(self.indeg, o),
+                             self._at(self.knn_mean, o))
+            j.rank = self._at(self.rank, 4 * o)
+            j.ensemble = self._at(self.ensemble, o)
+            j.knn_ids = self._at(self.knn_ids, self.off_k[i])
+            j.knn_dist = self._at(self.knn_dist, self.off_k[i])
+
+    @staticmethod
+    def _at(t: Optional[torch.Tensor], off: int):
+        return None if t is None else t.data_ptr() + off * t.element_size()
+
+    def __len__(self):
+        return len(self.specs)
+
+    def set_walk(self, i: int, mode: int, index_dims: int):
+        self.mode[i], self.index_dims[i] = int(mode), int(index_dims)
+        self.arr[i].mode, self.arr[i].index_dims = int(mode), int(index_dims)
+
+    def walk_specs(self):
+        """Lightweight per-job records (pop, mask, k, eps, mode, index_dims)
+        for the autotuner; ``apply_walk`` copies their settings back."""
+        from types import SimpleNamespace
+        return [SimpleNamespace(pop=p, mask=m, k=k, eps=e, mode=self.mode[i], index_dims=self.index_dims[i])
+                for i, (p, m, k, e) in enumerate(self.specs)]
+
+    def apply_walk(self, recs):
+        for i, r in enumerate(recs):
+            self.set_walk(i, r.mode, r.index_dims)
+
+    def c_ptr(self, start: int = 0):
+        return ctypes.cast(ctypes.byref(self.arr, start * ctypes.sizeof(c_job)), ctypes.POINTER(c_job))
+
+    def workspace_bytes(self, tune: Optional[c_tuning] = None, start: int = 0, stop: Optional[int] = None) -> int:
+        stop = len(self) if stop is None else stop
+        return int(load_library().snaps_outlier_scores_workspace(self.c_ptr(start), stop - start,
+                                                                 None if tune is None else ctypes.byref(tune)))
+
+    def run(self, tune: Optional[c_tuning] = None, ws: Optional[torch.Tensor] = None, stream=None,
+            start: int = 0, stop: Optional[int] = None):
+        """One direct call over jobs [start, stop)."""
+        lib = load_library()
+        stop = len(self) if stop is None else stop
+        tp = None if tune is None else ctypes.byref(tune)
+        if ws is None:
+            ws = _workspace(self.workspace_bytes(tune, start, stop), self.eps_count.device)
+        _check(lib.snaps_outlier_scores(self.c_ptr(start), stop - start, tp, _ptr(ws), ws.numel(), _stream(stream)))
+
+    def plans(self, stats: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None):
+        """(workspace, [index, join, rank] plans) over every job; ``stats``
+        accumulates the join pass's counters."""
+        tunes = [tuning(passes=p, stats=stats if p == PASS_JOIN else None) for p in (PASS_INDEX, PASS_JOIN, PASS_RANK)]
+        if ws is None:
+            ws = _workspace(self.workspace_bytes(tunes[1]), self.eps_count.device)
+        self._tunes = tunes
+        return ws, [Plan(None, t, ws=ws, stream=stream, c_jobs=self.c_ptr(), n_jobs=len(self)) for t in tunes]
+
+    def out(self, i: int) -> dict:
+        """Device views of job i's outputs."""
+        _, _, k, _ = self.specs[i]
+        a, b = self.off[i], self.off[i + 1]
+        n = b - a
+        o = {"eps_count": self.eps_count[a:b], "eps_mean": self.eps_mean[a:b], "indeg": self.indeg[a:b],
+             "knn_mean": self.knn_mean[a:b]}
+        o["rank"] = None if self.rank is None else self.rank[4 * a:4 * b].view(4, n)
+        o["ensemble"] = None if self.ensemble is None else self.ensemble[a:b]
+        ka, kb = self.off_k[i], self.off_k[i + 1]
+        o["knn_ids"] = None if self.knn_ids is None else self.knn_ids[ka:kb].view(n, k)
+        o["knn_dist"] = None if self.knn_dist is None else self.knn_dist[ka:kb].view(n, k)
+        return o
 
 
 def snaps_rank(eps_count: torch.Tensor, eps_mean: torch.Tensor, indeg: torch.Tensor, knn_mean: torch.Tensor,

@@ -13,8 +13,11 @@ checked for validity instead of equality:
 * eps: counts are exact for every object with no oracle distance in
   [eps(1 - tau), eps(1 + tau)]; such objects are exempt from the count and the
   mean.  Means of the others hold to tau.
-* in-degree: exact when no query is exempt; otherwise the sum is still n*k and
-  the differences are bounded by the exempt swaps.
+* in-degree: (i) exactly the in-degree recomputed from the GPU's own kNN
+  lists of the same call, after those lists pass the kNN rule above;
+  (ii) exactly the oracle's for every object that no exempt query lists
+  (in the oracle's lists or the GPU's), and everywhere when no query is
+  exempt.  The sum is n*k.
 * ranks: (i) exactly the dense ranks of the GPU's own metric values; (ii) for
   the integer metrics, equal to the oracle's ranks when the metric matched;
   (iii) for the float metrics, every pair whose oracle values differ by more
@@ -25,6 +28,17 @@ from __future__ import annotations
 import numpy as np
 
 TAU = 1e-5
+
+
+def knn_strict(dk, dn) -> np.ndarray:
+    """Queries whose kNN set the GPU must reproduce exactly: oracle gap
+    (D_(k+1) - D_(k)) / D_(k+1) above tau, no (k+1)-th object, or exact
+    duplicates at both ranks."""
+    dk = np.asarray(dk, dtype=np.float64)
+    dn = np.asarray(dn, dtype=np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        gap = np.where(np.isinf(dn), np.inf, (dn - dk) / np.where(dn > 0, dn, 1.0))
+    return (gap > TAU) | ((dk == 0) & (dn == 0))
 
 
 def dense_rank_desc(values: np.ndarray) -> np.ndarray:
@@ -62,12 +76,8 @@ def _order_agrees(oracle_vals, gpu_rank, mask) -> int:
     neg = -v
     cut = np.searchsorted(neg, -thresh, side="left")   # number of elements with v > thresh
     pmax = np.maximum.accumulate(r)
-    bad = 0
-    for b in range(v.size):
-        c = cut[b]
-        if c > 0 and pmax[c - 1] >= r[b]:
-            bad += 1
-    return bad
+    has = cut > 0
+    return int((pmax[cut[has] - 1] >= r[has]).sum())
 
 
 def check_scores(gpu: dict, ora: dict, k: int, eps: float, check_ranks: bool = True, label: str = "") -> dict:
@@ -78,8 +88,7 @@ def check_scores(gpu: dict, ora: dict, k: int, eps: float, check_ranks: bool = T
     # kNN exemptions from the oracle's k-th / (k+1)-th distances
     dk = ora["knn_dist"][:, k - 1]
     dn = ora["knn_next"]
-    gap = np.where(np.isinf(dn), np.inf, (dn - dk) / np.where(dn > 0, dn, 1.0))
-    knn_exempt = ~((gap > TAU) | ((dk == 0) & (dn == 0)))
+    knn_exempt = ~knn_strict(dk, dn)
     rep["knn_exempt"] = int(knn_exempt.sum())
 
     # knn_mean within tau everywhere
@@ -107,10 +116,24 @@ def check_scores(gpu: dict, ora: dict, k: int, eps: float, check_ranks: bool = T
     # in-degree
     dg = np.asarray(gpu["indeg"]).astype(np.int64)
     assert dg.sum() == n * k, f"{label} in-degree sums to {dg.sum()}, not {n * k}"
-    if rep["knn_exempt"] == 0:
+    if gpu.get("knn_ids") is not None:
+        ids_g = np.asarray(gpu["knn_ids"]).astype(np.int64)
+        check_knn(ids_g, gpu["knn_dist"], ora, k, label=label)
+        # (i) the GPU's in-degree is the in-degree of its own (validated) lists
+        own = np.bincount(ids_g.ravel(), minlength=n)
+        assert (dg == own).all(), f"{label} in-degree differs from its own kNN lists at {np.nonzero(dg != own)[0][:5]}"
+        # (ii) objects no exempt query lists (either side) match the oracle
+        touched = np.zeros(n, dtype=bool)
+        touched[ora["knn_ids"][knn_exempt].ravel()] = True
+        touched[ids_g[knn_exempt].ravel()] = True
+        rep["indeg_exempt"] = int(touched.sum())
+        ok = (dg == ora["indeg"]) | touched
+        assert ok.all(), f"{label} in-degree off the oracle at {np.nonzero(~ok)[0][:5]}"
+    elif rep["knn_exempt"] == 0:
         assert (dg == ora["indeg"]).all(), f"{label} in-degree off at {np.nonzero(dg != ora['indeg'])[0][:5]}"
     else:
-        assert np.abs(dg - ora["indeg"]).sum() <= 2 * rep["knn_exempt"] * k
+        raise AssertionError(f"{label}: {rep['knn_exempt']} exempt queries and no GPU kNN lists to check "
+                             "the in-degree against")
 
     if check_ranks and gpu.get("rank") is not None:
         rg = np.asarray(gpu["rank"]).astype(np.int64)
@@ -136,20 +159,24 @@ def check_knn(ids_g, dist_g, ora: dict, k: int, label: str = "", row_ids=None) -
     dist_g = np.asarray(dist_g, dtype=np.float64)
     dk = ora["knn_dist"][:, k - 1]
     dn = ora["knn_next"]
-    gap = np.where(np.isinf(dn), np.inf, (dn - dk) / np.where(dn > 0, dn, 1.0))
-    strict = (gap > TAU) | ((dk == 0) & (dn == 0))
+    strict = knn_strict(dk, dn)
     n = ids_g.shape[0]
     if row_ids is None:
         row_ids = np.arange(n)
+    row_ids = np.asarray(row_ids).astype(np.int64)
     assert (np.diff(dist_g, axis=1) >= 0).all(), f"{label} GPU distances not ascending"
-    for i in range(n):
-        if strict[i]:
-            assert set(ids_g[i].tolist()) == set(ora["knn_ids"][i].tolist()), f"{label} kNN set of {i} differs"
-        else:
-            inner = ora["knn_ids"][i][ora["knn_dist"][i] < dk[i] * (1 - TAU)]
-            assert set(inner.tolist()) <= set(ids_g[i].tolist()), f"{label} exempt {i} misses a strict neighbour"
-            assert (dist_g[i] <= dk[i] * (1 + TAU) + 1e-30).all()
-        assert int(row_ids[i]) not in set(ids_g[i].tolist()), f"{label} object {row_ids[i]} is its own neighbour"
+    # every row holds k distinct ids in [0, N), never its own
+    srt = np.sort(ids_g, axis=1)
+    assert (srt[:, 1:] != srt[:, :-1]).all() if k > 1 else True, f"{label} a kNN list repeats an id"
+    assert (ids_g >= 0).all() and (ids_g != row_ids[:, None]).all(), f"{label} invalid id or own id in a list"
+    # strict rows: the oracle's set exactly
+    o_srt = np.sort(np.asarray(ora["knn_ids"]).astype(np.int64), axis=1)
+    bad = np.nonzero(strict & (srt != o_srt).any(axis=1))[0]
+    assert bad.size == 0, f"{label} kNN sets differ at {bad[:5]}"
+    for i in np.nonzero(~strict)[0]:
+        inner = ora["knn_ids"][i][ora["knn_dist"][i] < dk[i] * (1 - TAU)]
+        assert set(inner.tolist()) <= set(ids_g[i].tolist()), f"{label} exempt {i} misses a strict neighbour"
+        assert (dist_g[i] <= dk[i] * (1 + TAU) + 1e-30).all()
     od = ora["knn_dist"]
     rel = np.abs(np.sort(dist_g, axis=1) - od) / np.maximum(od, 1e-30)
     assert ((rel <= TAU) | ((od == 0) & (dist_g == 0))).all(), f"{label} kNN distances off"

@@ -31,14 +31,18 @@ def S():
     return snaps
 
 
+def job_out(job):
+    """Host copies of a job's outputs (the kNN lists too when it has them)."""
+    keys = ("eps_count", "eps_mean", "indeg", "knn_mean", "rank", "knn_ids", "knn_dist")
+    return {key: (None if getattr(job, key) is None else getattr(job, key).cpu().numpy()) for key in keys}
+
+
 def run_gpu(S, x, mask, k, eps, tune=None, with_rank=True):
     pop = S.Population.from_rows(x)
-    job = S.Job.alloc(pop, mask, k, eps, with_rank)
+    job = S.Job.alloc(pop, mask, k, eps, with_rank, with_lists=True)
     S.snaps_outlier_scores([job], tune)
     torch.cuda.synchronize()
-    out = {key: getattr(job, key).cpu().numpy() for key in ("eps_count", "eps_mean", "indeg", "knn_mean")}
-    out["rank"] = job.rank.cpu().numpy() if with_rank else None
-    return out
+    return job_out(job)
 
 
 def run_oracle(x, mask, k, eps):
@@ -152,11 +156,10 @@ def test_matrix_core_prefilter_every_d_and_k(S, d):
     ks = (1, 5, 10, 20, 32)
     outs = {}
     for filt in (1, 3):
-        jobs = [S.Job.alloc(pop, mask, k, eps) for k in ks]
+        jobs = [S.Job.alloc(pop, mask, k, eps, with_lists=True) for k in ks]
         S.snaps_outlier_scores(jobs, S.tuning(split=1, filter=filt))
         torch.cuda.synchronize()
-        outs[filt] = [{key: getattr(j, key).cpu().numpy() for key in ("eps_count", "eps_mean", "indeg", "knn_mean",
-                                                                       "rank")} for j in jobs]
+        outs[filt] = [job_out(j) for j in jobs]
     for k, a, b in zip(ks, outs[1], outs[3]):
         for key in a:
             np.testing.assert_array_equal(a[key], b[key], err_msg=f"{key} d={d} k={k}")
@@ -285,7 +288,7 @@ def test_batched_equals_single(S):
         k = int(rng.choice([5, 10, 20]))
         specs.append((mask, k, 0.05 * math.sqrt(d)))
     tune = S.tuning(split=1)
-    jobs = [S.Job.alloc(pop, m, k, e) for m, k, e in specs]
+    jobs = [S.Job.alloc(pop, m, k, e, with_lists=True) for m, k, e in specs]
     S.snaps_outlier_scores(jobs, tune)
     torch.cuda.synchronize()
     for (m, k, e), job in zip(specs, jobs):
@@ -295,8 +298,7 @@ def test_batched_equals_single(S):
         for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
             assert torch.equal(getattr(job, key), getattr(single, key)), f"{key} mask={m:x}"
     for (m, k, e), job in list(zip(specs, jobs))[:4]:
-        g = {key: getattr(job, key).cpu().numpy() for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank")}
-        check_scores(g, run_oracle(x, m, k, e), k, e, label=f"batched mask={m:x}")
+        check_scores(job_out(job), run_oracle(x, m, k, e), k, e, label=f"batched mask={m:x}")
 
 
 def test_knn_and_eps_entry_points(S):
@@ -400,8 +402,7 @@ def sampled_check(S, x, mask, k, eps, jobs_out, n_samples=384, seed=0, label="")
     return int(exempt.sum())
 
 
-def _out(job):
-    return {key: getattr(job, key).cpu().numpy() for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank")}
+_out = job_out
 
 
 @pytest.mark.parametrize("n,d", [(32769, 3), (100_000, 2), (100_000, 6), (150_000, 12)])
@@ -492,7 +493,7 @@ def test_lockstep_workgroups(S, mq):
     specs = [(0b111, 5, 0.05), (0b1111100000, 10, 0.3), (0x7FFF, 20, 0.6), (0b11, 10, 0.01)]
     for mask, k, eps in specs:
         a = S.Job.alloc(pop, mask, k, eps)
-        b = S.Job.alloc(pop, mask, k, eps)
+        b = S.Job.alloc(pop, mask, k, eps, with_lists=True)
         S.snaps_outlier_scores([a], S.tuning(split=1, mq=1))
         S.snaps_outlier_scores([b], S.tuning(split=1, mq=mq))
         torch.cuda.synchronize()
@@ -528,6 +529,13 @@ def test_graph_plans_replay(S):
             for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
                 assert torch.equal(getattr(a, key), getattr(b, key)), f"replay {rep} {key}"
         del junk
+    # the join pass alone, replayed again and again, recomputes the same
+    # in-degrees (it clears them itself before adding)
+    for rep in range(3):
+        plans[1].launch()
+        torch.cuda.synchronize()
+        for a, b in zip(ref, jobs):
+            assert torch.equal(a.indeg, b.indeg), f"join-only replay {rep}"
     single = [S.Job.alloc(pop, *specs[0])]
     whole = S.Plan(single, S.tuning())
     whole.launch()
@@ -874,13 +882,12 @@ def test_per_job_walk_settings_and_autotuner(S):
     epss = [0.08 * math.sqrt(bin(m).count("1")) for m in masks]
 
     def run(settings, jobs=None):
-        jobs = jobs or [S.Job.alloc(pop, m, 10, e) for m, e in zip(masks, epss)]
+        jobs = jobs or [S.Job.alloc(pop, m, 10, e, with_lists=True) for m, e in zip(masks, epss)]
         for j, (mo, c) in zip(jobs, settings):
             j.mode, j.index_dims = mo, c
         S.snaps_outlier_scores(jobs, S.tuning(split=1))
         torch.cuda.synchronize()
-        return [{key: getattr(j, key).cpu().numpy() for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank")}
-                for j in jobs]
+        return [job_out(j) for j in jobs]
 
     def same(a, b, label):
         for ra, rb in zip(a, b):
