@@ -227,6 +227,29 @@ int snaps_plan_create(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning*
 int snaps_plan_launch(const snaps_plan* plan, void* stream);
 void snaps_plan_destroy(snaps_plan* plan);
 
+/* snaps_outlier_scores without a workspace argument and without any device
+ * allocation, for callers that cannot allocate device memory: code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The scratch space is a fixed array of SNAPS_STATIC_SCRATCH_BYTES inside
+ * the library, one per device, held until the process ends (its address is
+ * looked up once per device, on the first call with that device current).
+ * Same jobs, tuning, outputs and results as snaps_outlier_scores (the same
+ * kernels run); inputs and outputs remain caller memory.
+ *   Returns SNAPS_ENOMEM (nothing launched) when the jobs need more scratch
+ *   than SNAPS_STATIC_SCRATCH_BYTES, i.e. when
+ *   snaps_outlier_scores_workspace(jobs, n_jobs, tune) exceeds it (about
+ *   2.8 MB per job of 31,693 objects at d = 15; one job of up to ~700,000
+ *   objects at d = 15).
+ *   Every call on a device shares that device's array and leaves its
+ *   contents behind; the kernels initialise what they read.  Calls that
+ *   overlap on one device (other streams, other threads) race on the array:
+ *   serialise them.  As with snaps_outlier_scores, the job table is copied
+ *   from host memory (into the array), which may wait for earlier work on
+ *   `stream`. */
+#define SNAPS_STATIC_SCRATCH_BYTES (64u << 20)
+int snaps_outlier_scores_static(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune,
+                                void* stream);
+
 /* Dense rankings of the four metrics of one job (Sec. 3.4, Tab. 2): rank 0
  * is the most outlying; eps_count and indeg rank ascending, eps_mean and
  * knn_mean descending, and objects with eps_count == 0 rank first on

@@ -930,6 +930,62 @@ void snaps_plan_destroy(snaps_plan* plan) {
     delete plan;
 }
 
+}  // extern "C"
+
+// ------------------------------------------- allocation-free batched form
+
+// The workspace of snaps_outlier_scores_static: one fixed array per device,
+// part of the library's code object, held until the process ends.  Host code
+// never uses this name as an address (on the host it is only a stand-in):
+// every use goes through the device address that hipGetSymbolAddress
+// returns, looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[SNAPS_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+int static_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(SNAPS_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return SNAPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int snaps_outlier_scores_static(const snaps_job* jobs, int32_t n_jobs, const snaps_tuning* tune, void* stream) {
+    int rc = check_tuning(tune);
+    if (rc != SNAPS_OK) return rc;
+    std::vector<RunJob> rj;
+    rc = collect_jobs(jobs, n_jobs, tune, &rj);
+    if (rc != SNAPS_OK) return rc;
+    const size_t need = run_workspace(rj);
+    if (need > (size_t)SNAPS_STATIC_SCRATCH_BYTES)
+        return fail(SNAPS_ENOMEM,
+                    "these jobs need %zu bytes of workspace, more than the %zu of the static scratch: "
+                    "use snaps_outlier_scores with a caller workspace",
+                    need, (size_t)SNAPS_STATIC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    rc = static_scratch(&ws);
+    if (rc != SNAPS_OK) return rc;
+    return run(rj, resolve_tune(tune), ws, SNAPS_STATIC_SCRATCH_BYTES, static_cast<hipStream_t>(stream));
+}
+
+
 // ------------------------------------------------------------------ serving
 
 namespace {

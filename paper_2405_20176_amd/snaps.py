@@ -117,6 +117,8 @@ def load_library(path: str = LIB_PATH):
     lib.snaps_outlier_scores.argtypes = [P(c_job), i32, P(c_tuning), vp, sz, vp]
     lib.snaps_rank.restype = ctypes.c_int
     lib.snaps_rank.argtypes = [vp, vp, vp, vp, i64, vp, vp, sz, vp]
+    lib.snaps_outlier_scores_static.restype = ctypes.c_int
+    lib.snaps_outlier_scores_static.argtypes = [P(c_job), i32, P(c_tuning), vp]
     lib.snaps_plan_create.restype = ctypes.c_int
     lib.snaps_plan_create.argtypes = [P(c_job), i32, P(c_tuning), vp, sz, vp, P(vp)]
     lib.snaps_plan_launch.restype = ctypes.c_int
@@ -317,6 +319,18 @@ def snaps_outlier_scores(jobs: Sequence[Job], tune: Optional[c_tuning] = None, w
     if ws is None:
         ws = _workspace(need, jobs[0].pop.cols.device)
     _check(lib.snaps_outlier_scores(arr, len(jobs), tp, _ptr(ws), ws.numel(), _stream(stream)))
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def snaps_outlier_scores_static(jobs: Sequence[Job], tune: Optional[c_tuning] = None, stream=None):
+    """snaps_outlier_scores with the library's static per-device scratch
+    (no workspace argument, no device allocation)."""
+    lib = load_library()
+    arr = _c_jobs(jobs)
+    tp = None if tune is None else ctypes.byref(tune)
+    _check(lib.snaps_outlier_scores_static(arr, len(jobs), tp, _stream(stream)))
 
 
 class Plan:

@@ -244,3 +244,27 @@ def test_k_grid_validation(lib):
     assert lib.snaps_k_grid_workspace(ctypes.byref(big), 1) > 0
     big.k[2] = 4097
     assert lib.snaps_k_grid_workspace(ctypes.byref(big), 1) == 0
+
+
+def test_static_scratch_entry_validation(lib):
+    """The allocation-free form validates like snaps_outlier_scores and
+    refuses, before any device work, jobs whose workspace exceeds its fixed
+    scratch."""
+    from paper_2405_20176_amd.snaps import STATIC_SCRATCH_BYTES, c_job, c_population, c_scores
+    p = _pop()
+    job = c_job()
+    job.pop = ctypes.pointer(p)
+    job.mask, job.k, job.eps = 0b111, 5, 0.1
+    job.out = c_scores(0x10, 0x20, 0x30, 0x40)
+    assert lib.snaps_outlier_scores_static(ctypes.byref(job), 0, None, None) == -1
+    bad = c_job.from_buffer_copy(job)
+    bad.k = 0
+    assert lib.snaps_outlier_scores_static(ctypes.byref(bad), 1, None, None) == -1
+    big = c_population(0x1000, 1_200_000, 1_200_000, 15)
+    bj = c_job.from_buffer_copy(job)
+    bj.pop = ctypes.pointer(big)
+    bj.mask = (1 << 15) - 1
+    assert lib.snaps_outlier_scores_workspace(ctypes.byref(bj), 1, None) > STATIC_SCRATCH_BYTES
+    rc = lib.snaps_outlier_scores_static(ctypes.byref(bj), 1, None, None)
+    assert rc == -2, lib.snaps_last_error()
+    assert b"static scratch" in lib.snaps_last_error()
