@@ -75,66 +75,329 @@ def cpu_baseline(x, masks, eps_tab, k):
             "extrapolated_s": total, "cpu_model": _cpu_model()}
 
 
-def serve_bench(S, G, dev, seconds: float, spaces_per_pop: int = 4, n_streams: int = 4):
+def serve_bench(S, G, dev, seconds: float, warmup_s: float = 10.0, n_streams: int = 4, plain_s: float = 20.0,
+                capacity_s: float = 10.0):
     """Served form: 4 resident populations of 1,000,000 objects (the serving
-    generator), the first `spaces_per_pop` subspaces of each population's
-    seeded catalogue resident as scoring states, and an open-loop Poisson
-    stream (200 requests/s, 1..10,000 alerts per request, log-uniform) replayed
-    in real time through the continuous-batching server.  Requests naming a
-    non-resident catalogue entry are mapped onto the resident ones."""
+    generator), every subspace of each population's seeded catalogue (64 per
+    population, 256 states) built at start-up (cold builds, timed one by one),
+    and an open-loop Poisson stream (200 requests/s, 1..10,000 alerts per
+    request, log-uniform) replayed in real time through the
+    continuous-batching server: ``warmup_s`` seconds of arrivals whose
+    requests are served but not counted, then ``seconds`` measured.
+    Compared with the plain form (one request at a time, each alone, no
+    overlap) on the same states: both serve the same backlog of requests as
+    fast as they can (capacity, results compared bit for bit), and the plain
+    form replays ``plain_s`` seconds of the same arrivals."""
     import torch
-    from paper_2405_20176_amd.serve import Admission, Batcher, GpuExecutor, Request
+    from paper_2405_20176_amd.serve import Admission, Batcher, GpuExecutor, Request, serve_serial
     w = G.gen_c4()
     masks_tab, eps_tab = G.load_c4_eps()
     t0 = time.perf_counter()
-    pops, bounds, states = [], [], {}
+    bounds, states = [], {}
     build_s = []
+    pops = []
     for p in range(w.n_pop):
         x, lo, hi = w.population(p)
         pop = S.Population.from_rows(x, device=dev)
         del x
         pops.append(pop)
         bounds.append((lo, hi))
-        for si in range(spaces_per_pop):
-            m = int(masks_tab[p, si])
-            assert m == int(w.spaces[p][si])
+        assert np.array_equal(masks_tab[p], w.spaces[p]), "eps table does not match the serving catalogue"
+        for si, m in enumerate(int(v) for v in masks_tab[p]):
             tb = time.perf_counter()
             states[(p, m)] = S.ServeState(pop, m, w.k, float(eps_tab[p, si]))
             torch.cuda.synchronize()
             build_s.append(time.perf_counter() - tb)
-    log(f"serving: {len(states)} states built in {time.perf_counter() - t0:.1f} s "
-        f"(cold build per state {np.median(build_s):.2f} s median)")
+    state_bytes = sum(st.nbytes for st in states.values())
+    log(f"serving: {len(states)} states ({state_bytes / 2**30:.1f} GiB) built in {time.perf_counter() - t0:.1f} s "
+        f"(cold build per state {np.median(build_s):.3f} s median)")
+    tg = time.perf_counter()
     reqs = []
-    for r in w.requests(seconds):
+    for r in w.requests(warmup_s + seconds):
         p = r.pop
-        m = int(masks_tab[p, r.space % spaces_per_pop])
+        m = int(masks_tab[p, r.space])
         cols = G.mask_features(m)
         lo, hi = bounds[p]
         al = np.ascontiguousarray(w.alerts(r, lo, hi)[:, cols], dtype=np.float32)
         reqs.append(Request(r.rid, r.arrival_s, (p, m), al))
-    n_alerts = sum(q.m for q in reqs)
-    log(f"serving: {len(reqs)} requests, {n_alerts} alerts over {seconds:.0f} s of arrivals")
+    log(f"serving: {len(reqs)} requests over {warmup_s + seconds:.0f} s of arrivals generated in "
+        f"{time.perf_counter() - tg:.1f} s")
     ex = GpuExecutor(states, n_streams=n_streams, device=dev)
-    # warm-up: one request per state, not timed
     warm = Batcher(ex, Admission(8 << 30, n_streams))
     for i, key in enumerate(states):
         warm.submit(Request(-1 - i, 0.0, key, np.zeros((64, bin(key[1]).count("1")), np.float32)))
     warm.drain()
+    fresh = lambda rs: [Request(r.rid, r.arrival, r.key, r.alerts) for r in rs]
+
+    # continuous batching, open loop
     b = Batcher(ex, Admission(8 << 30, n_streams), max_batch_alerts=1 << 16)
     t_start = time.perf_counter()
-    b.run_open_loop(reqs)
-    t_end = time.perf_counter()
-    lat = b.latencies()
-    done = [r for r in b.finished if r.status == "done"]
-    span = max(r.done for r in done) - min(r.arrival for r in done)
+    b.run_open_loop(fresh(reqs), t0=t_start)
+    wall = time.perf_counter() - t_start
+    meas = [r for r in b.finished if r.status == "done" and r.arrival - t_start >= warmup_s]
+    lat = np.array([r.done - r.arrival for r in meas])
+    span = max(r.done for r in meas) - min(r.arrival for r in meas)
     res = {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-           "mean_ms": float(lat.mean() * 1e3), "requests": len(done), "rejected": len(b.finished) - len(done),
-           "alerts": int(sum(r.m for r in done)), "alert_scores_per_s": float(sum(r.m for r in done) / span),
-           "wall_s": t_end - t_start, "arrival_rate_hz": w.rate_hz, "populations": w.n_pop, "population_n": w.pop_n,
-           "resident_states": len(states), "state_build_s_median": float(np.median(build_s)), "k": w.k,
-           "form": "continuous batching over 4 streams, admission by an 8 GiB in-flight budget"}
-    log(f"serving: p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms, "
+           "mean_ms": float(lat.mean() * 1e3), "max_ms": float(lat.max() * 1e3), "requests": len(meas),
+           "rejected": sum(1 for r in b.finished if r.status != "done"),
+           "alerts": int(sum(r.m for r in meas)), "alert_scores_per_s": float(sum(r.m for r in meas) / span),
+           "requests_per_s": len(meas) / span, "measured_s": seconds, "warmup_s": warmup_s, "wall_s": wall,
+           "arrival_rate_hz": w.rate_hz, "populations": w.n_pop, "population_n": w.pop_n,
+           "resident_states": len(states), "resident_state_gib": state_bytes / 2**30,
+           "cold_builds": {"count": len(build_s), "median_s": float(np.median(build_s)),
+                           "max_s": float(np.max(build_s)), "total_s": float(np.sum(build_s)),
+                           "when": "at start-up, before the first request (every catalogue state resident; no "
+                                   "request meets a missing state)"},
+           "cold_misses": 0, "k": w.k, "batches": b.batches_launched, "max_batches_in_flight": b.max_inflight,
+           "form": f"continuous batching over {n_streams} streams, admission by an 8 GiB in-flight budget, "
+                   "latency = completion (results in host memory) - arrival"}
+    log(f"serving: p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms over {len(meas)} requests, "
         f"{res['alert_scores_per_s']:.3e} alert scores/s")
+
+    # capacity: the same backlog served as fast as possible, batched vs plain
+    back = [r for r in reqs if warmup_s <= r.arrival < warmup_s + capacity_s]
+    bq = fresh(back)
+    for r in bq:
+        r.arrival = 0.0
+    bb = Batcher(ex, Admission(8 << 30, n_streams), max_batch_alerts=1 << 16)
+    tc = time.perf_counter()
+    bb.run_open_loop(bq, t0=tc)
+    cap_batched_s = time.perf_counter() - tc
+    pq = fresh(back)
+    tc = time.perf_counter()
+    pdone = serve_serial(ex, pq, open_loop=False)
+    cap_plain_s = time.perf_counter() - tc
+    got = {r.rid: r.result for r in bb.finished}
+    same = all(np.array_equal(got[r.rid][key], r.result[key]) for r in pdone for key in r.result)
+    n_al = int(sum(r.m for r in back))
+    cap = {"requests": len(back), "alerts": n_al, "batched_s": cap_batched_s, "plain_s": cap_plain_s,
+           "batched_alerts_per_s": n_al / cap_batched_s, "plain_alerts_per_s": n_al / cap_plain_s,
+           "results_identical": bool(same),
+           "what": f"the requests arriving in [{warmup_s:.0f}, {warmup_s + capacity_s:.0f}) s, all queued at once"}
+    res["capacity"] = cap
+    res["served_over_plain"] = cap["batched_alerts_per_s"] / cap["plain_alerts_per_s"]
+    log(f"serving capacity: batched {cap['batched_alerts_per_s']:.3e} vs plain {cap['plain_alerts_per_s']:.3e} "
+        f"alerts/s (identical results: {same})")
+
+    # the plain form under the same arrivals (a shorter slice)
+    if plain_s > 0:
+        sl = fresh([r for r in reqs if r.arrival < warmup_s + plain_s])
+        tp = time.perf_counter()
+        pd = serve_serial(ex, sl, open_loop=True)
+        pm = [r for r in pd if r.arrival - tp >= warmup_s]
+        pl = np.array([r.done - r.arrival for r in pm])
+        res["plain_open_loop"] = {"p50_ms": float(np.percentile(pl, 50) * 1e3),
+                                  "p99_ms": float(np.percentile(pl, 99) * 1e3), "requests": len(pm),
+                                  "measured_s": plain_s, "warmup_s": warmup_s,
+                                  "form": "one request at a time, each alone, same states and kernels"}
+        log(f"serving plain open loop: p50 {res['plain_open_loop']['p50_ms']:.1f} ms, "
+            f"p99 {res['plain_open_loop']['p99_ms']:.1f} ms")
+    del states, pops
+    return res
+
+
+def _c3_gen(job):
+    import snaps_synth as G
+    return job.index, G.gen_c3_projected(job)
+
+
+def c3_bench(S, G, lib, dev, stream, steps: int, warmup: int, autotune_sample: int, plain: bool):
+    """Batched uneven workload: 4,096 (population, subspace) jobs, each with
+    its own population (N log-uniform in [1e4, 5e5], the SNAPShot1-shaped
+    generator), d uniform in 2..15, k in {5, 10, 20}, eps from the stored
+    table (sampler target k).  Populations are held as their d subspace
+    columns.  The walk of each (d, log2 n) class comes from the autotuner
+    (measured on a few jobs per class before timing); the three passes of
+    the whole table are HIP graphs.  Compared with the plain form (one
+    library call per job, one stream)."""
+    import multiprocessing as mp
+    import torch
+    from paper_2405_20176_amd import autotune as AT
+    t0 = time.perf_counter()
+    jobs = G.gen_c3_jobs()
+    eps = G.load_c3_eps()
+    pops = [None] * len(jobs)
+    workers = max(1, min(16, os.cpu_count() or 4))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        for idx, x in pool.imap_unordered(_c3_gen, jobs, chunksize=4):
+            pops[idx] = S.Population.from_rows(x, device=dev)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    ns = np.array([j.n for j in jobs], dtype=np.int64)
+    ds = np.array([bin(j.mask).count("1") for j in jobs])
+    ks = np.array([j.k for j in jobs])
+    log(f"C3: {len(jobs)} populations ({ns.sum():.3e} objects, {sum(p.cols.numel() for p in pops) * 4 / 2**30:.1f} "
+        f"GiB of subspace columns) generated and uploaded in {t_gen:.1f} s")
+    specs = [(pops[i], (1 << int(ds[i])) - 1, int(ks[i]), float(eps[i])) for i in range(len(jobs))]
+    tab = S.JobTable(specs, with_rank=True)
+    tuned = None
+    if autotune_sample > 0:
+        ta = time.perf_counter()
+        recs = tab.walk_specs()
+        table = AT.tune(recs, sample=autotune_sample, reps=2)
+        AT.apply(recs, table)
+        tab.apply_walk(recs)
+        tuned = {"seconds": time.perf_counter() - ta, "sample_per_class": autotune_sample, "classes": len(table),
+                 "choice": {key: [v["mode"], v["index_dims"], v.get("tile_shape", 1)] for key, v in table.items()}}
+        log(f"C3: autotuned {len(table)} classes in {tuned['seconds']:.1f} s")
+    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    tp = time.perf_counter()
+    ws, plans = tab.plans(stats=stats)
+    log(f"C3: plans built in {time.perf_counter() - tp:.1f} s, workspace {ws.numel() / 2**30:.1f} GiB")
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    for _ in range(warmup):
+        for p in plans:
+            p.launch(stream)
+    torch.cuda.synchronize()
+    stats.zero_()
+    marks = []
+    tt = time.perf_counter()
+    for _ in range(steps):
+        m = [ev()]
+        for p in plans:
+            p.launch(stream)
+            m.append(ev())
+        marks.append(m)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - tt) / steps
+    total_n = float(ns.sum())
+    value = total_n / sec
+    join_ms = sum(m[1].elapsed_time(m[2]) for m in marks) / steps
+    pairs, scanned, skipped, pd = (stats.cpu().numpy().astype(np.float64) / steps)
+    launches = len(set(zip(ds.tolist(), ks.tolist())))
+    achieved = 3.0 * pd / (join_ms / 1000.0)
+    # every job's in-degrees sum to n k (each object lists k neighbours)
+    off = torch.tensor(tab.off, dtype=torch.int64, device=dev)
+    seg = torch.repeat_interleave(torch.arange(len(jobs), device=dev), off[1:] - off[:-1])
+    sums = torch.zeros(len(jobs), dtype=torch.int64, device=dev).index_add_(0, seg, tab.indeg.to(torch.int64))
+    indeg_ok = bool((sums.cpu().numpy() == ns * ks).all())
+    results = float((ns * ks).sum()) + float(tab.eps_count.sum(dtype=torch.int64).item())
+    res = {"value": value, "unit": UNIT, "ms_per_step": sec * 1000.0, "steps": steps, "warmup": warmup,
+           "jobs": len(jobs), "objects": total_n, "scores_per_step": total_n,
+           "passes_ms_per_step": {name: sum(m[i].elapsed_time(m[i + 1]) for m in marks) / steps
+                                  for i, name in enumerate(("index", "join", "rank"))},
+           "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_FP32_MFMA, "avg_launch_ms": join_ms / launches,
+                        "launches_per_step": launches, "flops_per_pair": "3d"},
+           "join": {"pairs_evaluated": pairs, "brute_force_pairs": float((ns.astype(np.float64) ** 2).sum()),
+                    "candidates_per_result": pairs / results, "tiles_scanned": scanned, "tiles_skipped": skipped},
+           "indeg_sums_equal_nk": indeg_ok, "generate_upload_s": t_gen, "autotune": tuned,
+           "form": "one job table, index/join/rank passes replayed as HIP graphs"}
+    log(f"C3: {sec:.2f} s per step, {value:.3e} scores/s, join {join_ms:.0f} ms, frac {achieved / PEAK_FP32_MFMA:.3f}")
+    for p in plans:
+        p.close()
+    del plans, ws
+    torch.cuda.empty_cache()
+    if plain:
+        need = max(tab.workspace_bytes(None, i, i + 1) for i in range(len(jobs)))
+        pws = torch.empty(need, dtype=torch.uint8, device=dev)
+        tab.run(None, ws=pws, stream=stream, start=0, stop=1)
+        torch.cuda.synchronize()
+        tq = time.perf_counter()
+        for i in range(len(jobs)):
+            tab.run(None, ws=pws, stream=stream, start=i, stop=i + 1)
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - tq
+        res["plain"] = {"value": total_n / plain_s, "unit": UNIT, "ms_per_pass": plain_s * 1000.0,
+                        "form": "one library call per job, one stream, the same per-job walk settings"}
+        res["batched_over_plain"] = value / res["plain"]["value"]
+        log(f"C3 plain: {plain_s:.2f} s per pass")
+    del tab, pops
+    torch.cuda.empty_cache()
+    return res
+
+
+def c2_bench(S, G, dev, stream, steps: int):
+    """LSST-scale population: N = 5,000,000 objects (the SNAPShot1-shaped
+    generator), the full 15-feature space plus all 105 two-feature spaces,
+    k = 10, eps from the stored table (target mean count 20), in one job
+    table with ranks, passes replayed as HIP graphs, walk settings from the
+    library defaults (box pruning with super-tile culls at d = 2, brute force
+    at d = 15)."""
+    import torch
+    t0 = time.perf_counter()
+    x, masks, k, _ = G.gen_c2()
+    eps = G.load_c2_eps()
+    n = x.shape[0]
+    pop = S.Population.from_rows(x, device=dev)
+    del x
+    log(f"C2: population {n} x 15 generated and uploaded in {time.perf_counter() - t0:.1f} s")
+    tab = S.JobTable([(pop, int(m), k, float(e)) for m, e in zip(masks, eps)], with_rank=True)
+    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    ws, plans = tab.plans(stats=stats)
+    dims = np.array([bin(int(m)).count("1") for m in masks])
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    for p in plans:                       # warm-up
+        p.launch(stream)
+    torch.cuda.synchronize()
+    res = {"objects": n, "spaces": len(masks), "k": k, "eps_target_mean_count": 20,
+           "scores_per_step": float(n) * len(masks), "steps": steps}
+    # the full space and the 105 two-feature spaces are timed as one table;
+    # the join's per-d split comes from one more pass per part with events
+    stats.zero_()
+    marks = []
+    tt = time.perf_counter()
+    for _ in range(steps):
+        m = [ev()]
+        for p in plans:
+            p.launch(stream)
+            m.append(ev())
+        marks.append(m)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - tt) / steps
+    join_ms = sum(m[1].elapsed_time(m[2]) for m in marks) / steps
+    pairs, scanned, skipped, pd = stats.cpu().numpy().astype(np.float64) / steps
+    res.update({"value": float(n) * len(masks) / sec, "unit": UNIT, "ms_per_step": sec * 1000.0,
+                "passes_ms_per_step": {name: sum(m[i].elapsed_time(m[i + 1]) for m in marks) / steps
+                                       for i, name in enumerate(("index", "join", "rank"))},
+                "roofline": {"bound": "mfma", "achieved": 3.0 * pd / (join_ms / 1000.0) / 1e12,
+                             "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+                             "frac": 3.0 * pd / (join_ms / 1000.0) / PEAK_FP32_MFMA,
+                             "launches_per_step": len(set(dims.tolist())), "flops_per_pair": "3d"},
+                "join": {"pairs_evaluated": pairs, "brute_force_pairs": float(n) * n * len(masks),
+                         "tiles_scanned": scanned, "tiles_skipped": skipped}})
+    for p in plans:
+        p.close()
+    del plans
+    # per part: the full space alone and the 105 two-feature spaces alone
+    parts = {}
+    for name, sl in (("d15", slice(0, 1)), ("d2_x105", slice(1, len(masks)))):
+        st = torch.zeros(4, dtype=torch.int64, device=dev)
+        s0, s1 = sl.start, sl.stop
+        tab.run(S.tuning(passes=S.PASS_INDEX), ws=ws, stream=stream, start=s0, stop=s1)
+        e0 = ev()
+        tab.run(S.tuning(passes=S.PASS_JOIN, stats=st), ws=ws, stream=stream, start=s0, stop=s1)
+        e1 = ev()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        pr, sc, sk, pdd = st.cpu().numpy().astype(np.float64)
+        cnt = float(tab.eps_count[tab.off[s0]:tab.off[s1]].sum(dtype=torch.int64).item())
+        parts[name] = {"join_ms": ms, "pairs": pr, "pairs_over_brute_force": pr / (float(n) * n * (s1 - s0)),
+                       "candidates_per_result": pr / (float(n) * k * (s1 - s0) + cnt),
+                       "tflops": 3.0 * pdd / (ms / 1000.0) / 1e12,
+                       "frac": 3.0 * pdd / (ms / 1000.0) / PEAK_FP32_MFMA,
+                       "tiles_scanned": sc, "tiles_skipped": sk}
+    res["parts"] = parts
+    off = torch.tensor(tab.off, dtype=torch.int64, device=dev)
+    sums = torch.stack([tab.indeg[tab.off[i]:tab.off[i + 1]].sum(dtype=torch.int64) for i in range(len(masks))])
+    res["indeg_sums_equal_nk"] = bool((sums.cpu().numpy() == n * k).all())
+    del off
+    log(f"C2: {sec:.2f} s per step, {res['value']:.3e} scores/s, join {join_ms:.0f} ms "
+        f"(d15 {parts['d15']['join_ms']:.0f} ms frac {parts['d15']['frac']:.2f}, "
+        f"105 x d2 {parts['d2_x105']['join_ms']:.0f} ms, {parts['d2_x105']['candidates_per_result']:.1f} cand/result)")
+    del tab, ws, pop
+    torch.cuda.empty_cache()
     return res
 
 
@@ -288,6 +551,44 @@ def _cpu_model():
     return "unknown"
 
 
+def per_d_breakdown(lib, S, jobs, dims, n, k, dev, stream, out_cnt):
+    """One eager index + join pass per dimensionality with its own counters
+    and HIP events (after the timed steps): join time, pairs evaluated,
+    candidates per result and the fraction of the fp32 peak, per d."""
+    import torch
+    sptr = ctypes.c_void_p(stream.cuda_stream)
+    out = {}
+    for d in sorted(set(int(v) for v in dims)):
+        idx = np.nonzero(dims == d)[0]
+        s0, cnt = int(idx[0]), int(idx.size)
+        assert idx[-1] - s0 + 1 == cnt
+        ptr = ctypes.cast(ctypes.byref(jobs, s0 * ctypes.sizeof(S.c_job)), ctypes.POINTER(S.c_job))
+        st = torch.zeros(4, dtype=torch.int64, device=dev)
+        t_idx, t_join = S.tuning(passes=S.PASS_INDEX), S.tuning(passes=S.PASS_JOIN, stats=st)
+        need = lib.snaps_outlier_scores_workspace(ptr, cnt, ctypes.byref(t_join))
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        wsp = ctypes.c_void_p(ws.data_ptr())
+        for t in (t_idx, t_join):      # a warm-up of both passes
+            if lib.snaps_outlier_scores(ptr, cnt, ctypes.byref(t), wsp, need, sptr) != 0:
+                raise RuntimeError(S.last_error())
+        st.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if lib.snaps_outlier_scores(ptr, cnt, ctypes.byref(t_join), wsp, need, sptr) != 0:
+            raise RuntimeError(S.last_error())
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        pairs, scanned, skipped, pd = st.cpu().numpy().astype(np.float64)
+        results = float(cnt) * n * k + float(out_cnt[s0:s0 + cnt].sum(dtype=torch.int64).item())
+        out[str(d)] = {"subspaces": cnt, "join_ms": ms, "pairs": pairs, "pairs_over_brute_force": pairs / (cnt * n * n),
+                       "candidates_per_result": pairs / results,
+                       "tiles_scanned": scanned, "tiles_skipped": skipped,
+                       "tflops": 3.0 * pd / (ms / 1000.0) / 1e12, "frac": 3.0 * pd / (ms / 1000.0) / PEAK_FP32_MFMA}
+        del ws
+    return out
+
+
 class _Eager:
     """One batched pass launched by a direct snaps_outlier_scores call (same
     interface as a captured plan)."""
@@ -309,7 +610,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=0, help="subspaces per batched plan (0: all in one)")
-    ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving run length (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="measured serving run length after a 10 s warm-up (0: skip serving)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-subspace pass")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--spaces", type=int, default=0, help="debug: use only the first N subspaces")
@@ -328,6 +630,16 @@ def main():
                     help="skip timing the k-grid selection on a slice of the subspaces")
     ap.add_argument("--grid-spaces", type=int, default=1024,
                     help="subspaces in the eps-grid and k-grid slices")
+    ap.add_argument("--no-per-d", dest="per_d", action="store_false",
+                    help="skip the per-dimensionality join breakdown (one eager pass per d after the timed steps)")
+    ap.add_argument("--no-c2", dest="c2", action="store_false",
+                    help="skip the LSST-scale population (5,000,000 objects, the full space + 105 two-feature spaces)")
+    ap.add_argument("--c2-steps", type=int, default=1, help="timed steps of the LSST-scale population")
+    ap.add_argument("--no-c3", dest="c3", action="store_false",
+                    help="skip the batched-uneven workload (4,096 jobs of their own populations)")
+    ap.add_argument("--c3-steps", type=int, default=2, help="timed steps of the batched-uneven workload")
+    ap.add_argument("--c3-autotune-sample", type=int, default=4,
+                    help="jobs timed per (d, log2 n) class by the autotuner on the batched-uneven workload (0: off)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain MIB-MiB device copy (counter calibration) and exit")
     a = ap.parse_args()
@@ -389,7 +701,8 @@ def main():
         from types import SimpleNamespace
         from paper_2405_20176_amd import autotune as AT
         t_at = time.perf_counter()
-        specs = [SimpleNamespace(pop=pop, mask=int(masks[i]), k=k, eps=float(eps_tab[i]), mode=0, index_dims=0)
+        specs = [SimpleNamespace(pop=pop, mask=int(masks[i]), k=k, eps=float(eps_tab[i]), mode=0, index_dims=0,
+                                 tile_shape=0)
                  for i in range(n_sp)]
         devname = AT.device_key(dev)
         table = AT.load(a.autotune_cache, devname) if a.autotune_cache else None
@@ -401,12 +714,15 @@ def main():
         AT.apply(specs, table)
         for i in range(n_sp):
             jobs[i].mode, jobs[i].index_dims = specs[i].mode, specs[i].index_dims
+            jobs[i].tile_shape = getattr(specs[i], "tile_shape", 0)
         tuned = {"seconds": time.perf_counter() - t_at, "source": source, "sample_per_class": a.autotune_sample,
-                 "choice": {key: [v["mode"], v["index_dims"]] for key, v in table.items()},
-                 "note": "mode 1 = every candidate tile, 2 = box pruning on index_dims indexed dimensions; "
+                 "choice": {key: [v["mode"], v["index_dims"], v.get("tile_shape", 1)] for key, v in table.items()},
+                 "note": "[mode, index_dims, tile_shape]: mode 1 = every candidate tile, 2 = box pruning on "
+                         "index_dims indexed dimensions; tile_shape 1 = 64-candidate tiles, 2 = 32-candidate "
+                         "halves culled by their own boxes; "
                          "measured per (d, log2 n) class on sampled jobs, outside the timed region"}
         log(f"autotune: {len(table)} classes in {tuned['seconds']:.1f} s: "
-            + ", ".join(f"{key}={v['mode']}/{v['index_dims']}" for key, v in table.items()))
+            + ", ".join(f"{key}={v['mode']}/{v['index_dims']}/{v.get('tile_shape', 1)}" for key, v in table.items()))
     chunk = a.chunk if a.chunk > 0 else n_sp
     chunks = [(s, min(n_sp, s + chunk)) for s in range(0, n_sp, chunk)]
     job_ptr = lambda s: ctypes.cast(ctypes.byref(jobs, s * ctypes.sizeof(S.c_job)), ctypes.POINTER(S.c_job))
@@ -509,6 +825,14 @@ def main():
         "autotune": tuned,
     }
 
+    if a.per_d:
+        del plans
+        torch.cuda.empty_cache()
+        plans = None
+        result["join_per_d"] = per_d_breakdown(lib, S, jobs, dims, n, k, dev, stream, out_cnt)
+        log("per d: " + ", ".join(f"d={d} {v['join_ms']:.0f} ms frac {v['frac']:.2f} pairs/bf {v['pairs_over_brute_force']:.2f}"
+                                  for d, v in result["join_per_d"].items()))
+
     if not a.no_plain:
         tune = S.tuning()
         per_ws = max(lib.snaps_outlier_scores_workspace(job_ptr(i), 1, ctypes.byref(tune)) for i in (0, n_sp - 1))
@@ -535,9 +859,14 @@ def main():
     if a.k_grid:
         result["k_grid_selection"] = k_grid_bench(S, pop, masks, n, dev, spaces=a.grid_spaces)
 
-    if a.serve_seconds > 0:
-        del plans
+    if a.c3 or a.c2 or a.serve_seconds > 0:
+        del plans, out_cnt, out_mean, out_deg, out_kmean, out_rank, out_ens
         torch.cuda.empty_cache()
+    if a.c3:
+        result["c3"] = c3_bench(S, G, lib, dev, stream, a.c3_steps, 1, a.c3_autotune_sample, not a.no_plain)
+    if a.c2:
+        result["c2"] = c2_bench(S, G, dev, stream, a.c2_steps)
+    if a.serve_seconds > 0:
         result["serving"] = serve_bench(S, G, dev, a.serve_seconds)
 
     if not a.no_cpu:

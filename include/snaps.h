@@ -105,6 +105,8 @@ typedef struct {
                                Fig. 1b) in ascending (distance, id) order -- the lists the
                                in-degree of this call was counted from */
     float* knn_dist;        /* [n][k] device or NULL: their Euclidean distances */
+    int32_t tile_shape;     /* 0: the call's snaps_tuning.tile_shape; else this job's (1, 2 or 3) */
+    int32_t reserved;       /* must be 0 */
 } snaps_job;
 
 /* Passes of snaps_outlier_scores (snaps_tuning.passes). */
@@ -136,7 +138,15 @@ typedef struct {
                                32,768 always use 2), 2 device-wide radix sort of full 32-bit
                                cell keys with the id as payload.  Results do not depend on it
                                beyond the summation order of the eps means. */
-    int32_t reserved;       /* must be 0 */
+    int32_t tile_shape;     /* how the matrix-core join walks the candidate tiles of a pruned job;
+                               results do not depend on it.  0 auto (3 for jobs of at least
+                               65,536 objects, else 1); 1: tiles in order of index distance, a
+                               64-query x 64-candidate tile pair screened when the candidate
+                               tile's bounding box is in reach (the leanest kernel); 2: as 3, and
+                               each candidate tile taken as two 32-object halves with boxes of
+                               their own, so a half out of reach of a 32-query block is not
+                               contracted (more box tests, fewer pairs); 3: as 1, with each run
+                               of 64 tiles culled as a whole by its box first (large jobs) */
     uint64_t* stats;        /* optional device uint64[4], accumulated (never cleared) by the
                                join pass: [0] query-candidate pairs evaluated, [1] candidate
                                tiles scanned, [2] candidate tiles skipped, [3] pairs evaluated

@@ -98,7 +98,7 @@ int check_tuning(const snaps_tuning* t) {
         return fail(SNAPS_EINVAL, "tuning.mq must be 0, 1, 2, 4 or 8");
     if (t->mq > 1 && t->split > 1) return fail(SNAPS_EINVAL, "tuning.mq and tuning.split cannot both exceed 1");
     if (t->index_sort < 0 || t->index_sort > 2) return fail(SNAPS_EINVAL, "tuning.index_sort must be 0, 1 or 2");
-    if (t->reserved != 0) return fail(SNAPS_EINVAL, "tuning.reserved must be zero");
+    if (t->tile_shape < 0 || t->tile_shape > 3) return fail(SNAPS_EINVAL, "tuning.tile_shape must be 0, 1, 2 or 3");
     return SNAPS_OK;
 }
 
@@ -132,7 +132,8 @@ struct JobPlan {
     bool large;              // index through the device-wide radix sort (full 32-bit cell keys)
     bool large_rank;         // ranks through the device-wide radix sort (n above one LDS)
     bool rank;               // rank scratch reserved
-    size_t xs_off, perm_off, box_off;
+    int32_t nsuper;
+    size_t xs_off, perm_off, box_off, sbox_off, hbox_off;
     size_t ihist_off, acc_off, sel_off;          // large index scratch
     size_t rkey_off, rpong_off, rhist_off, rnd_off;  // large rank scratch
     size_t bytes;
@@ -166,6 +167,11 @@ JobPlan plan_job(int64_t n, int d, int k, bool with_rank, int index_sort = kInde
     off += align_up(rows * sizeof(int32_t));
     p.box_off = off;
     off += align_up((size_t)p.ntiles * 2 * dp * sizeof(float));
+    p.nsuper = (p.ntiles + kSuper - 1) / kSuper;
+    p.sbox_off = off;
+    off += align_up((size_t)p.nsuper * 2 * dp * sizeof(float));
+    p.hbox_off = off;
+    off += align_up((size_t)p.ntiles * 4 * dp * sizeof(float));
     if (p.large) {
         p.ihist_off = off;
         off += align_up((size_t)256 * p.nchunks * sizeof(int32_t));
@@ -188,14 +194,30 @@ JobPlan plan_job(int64_t n, int d, int k, bool with_rank, int index_sort = kInde
     return p;
 }
 
-constexpr int kNumClasses = (kMaxD + 1) * 5;
-int class_id(int d, int kc) {
+// Kernel classes of the join: (dimensionality, top-k capacity, walk).
+constexpr int kNumClasses = (kMaxD + 1) * 5 * 2;
+int class_id(int d, int kc, int hier) {
     const int ki = kc == 0 ? 0 : kc == 5 ? 1 : kc == 10 ? 2 : kc == 20 ? 3 : 4;
-    return d * 5 + ki;
+    return (d * 5 + ki) * 2 + (hier ? 1 : 0);
 }
+constexpr int kKcOfClass[5] = {0, 5, 10, 20, 32};
+int class_d(int c) { return c / 10; }
+int class_kc(int c) { return kKcOfClass[(c / 2) % 5]; }
+int class_hier(int c) { return c % 2; }
+
+// Tile shape of a job (snaps_tuning.tile_shape): 1 = the lean walk over
+// 64-candidate tiles, 2 = super-tile culls and 32-candidate halves, 3 =
+// super-tile culls over whole tiles.  Automatic: 3 for pruned jobs with at
+// least kHierMinSupers super-tiles, else 1.
+constexpr int kHierMinSupers = 16;
+int resolve_shape(int shape, const JobPlan& p, int prune) {
+    if (shape == 0) shape = (prune && p.nsuper >= kHierMinSupers) ? 3 : 1;
+    return shape;
+}
+bool shape_hier(int shape, int prune) { return prune && (shape == 2 || shape == 3); }
 
 struct MetaLayout {
-    size_t table, order, unit_prefix, tile_prefix, counters;
+    size_t table, order, unit_prefix, tile_prefix, super_prefix, counters;
     size_t li, iseg, ichunk, lr, rseg, rchunk, rsegchunk;
     size_t bytes;
 };
@@ -212,6 +234,7 @@ MetaLayout meta_layout(int n_jobs, int n_large, int n_lrank) {
     m.order = take((size_t)n_jobs * sizeof(int32_t));
     m.unit_prefix = take((size_t)(n_jobs + kNumClasses * kQueues) * sizeof(int32_t));
     m.tile_prefix = take((size_t)(n_jobs + 1) * sizeof(int32_t));
+    m.super_prefix = take((size_t)(n_jobs + 1) * sizeof(int32_t));
     m.counters = take((size_t)kNumClasses * kQueues * sizeof(int32_t));
     m.li = take((size_t)n_large * sizeof(LargeIndex));
     m.iseg = take((size_t)n_large * sizeof(SortSeg));
@@ -225,7 +248,7 @@ MetaLayout meta_layout(int n_jobs, int n_large, int n_lrank) {
 }
 
 struct Tune {
-    int mode = 0, split = 0, index_dims = 0, filter = 0, passes = 7, mq = 0;
+    int mode = 0, split = 0, index_dims = 0, filter = 0, passes = 7, mq = 0, tile_shape = 0;
     unsigned long long* stats = nullptr;
 };
 
@@ -238,6 +261,7 @@ Tune resolve_tune(const snaps_tuning* t) {
         r.filter = t->filter;
         r.passes = t->passes ? t->passes : 7;
         r.mq = t->mq;
+        r.tile_shape = t->tile_shape;
         r.stats = reinterpret_cast<unsigned long long*>(t->stats);
     }
     return r;
@@ -275,6 +299,12 @@ DevJob make_devjob(const snaps_population* P, uint32_t mask, const JobPlan& p, f
     j.xs = reinterpret_cast<float*>(ws_base + p.xs_off);
     j.perm = reinterpret_cast<int32_t*>(ws_base + p.perm_off);
     j.boxes = reinterpret_cast<float*>(ws_base + p.box_off);
+    j.sboxes = reinterpret_cast<float*>(ws_base + p.sbox_off);
+    j.hboxes = reinterpret_cast<float*>(ws_base + p.hbox_off);
+    j.nsuper = p.nsuper;
+    const int shape = resolve_shape(tn.tile_shape, p, j.prune);
+    j.halves = shape == 2 && j.prune ? 1 : 0;
+    j.hier = shape_hier(shape, j.prune) ? 1 : 0;
     return j;
 }
 
@@ -327,9 +357,9 @@ int launch_joins(const Meta& meta, const std::vector<ClassPlan>& plans, const Tu
     for (int c = 0; c < kNumClasses; ++c) {
         const ClassPlan& p = plans[c];
         if (p.count == 0) continue;
-        const int d = c / 5;
-        static const int kKc[5] = {0, 5, 10, 20, 32};
-        const int kc = kKc[c % 5];
+        const int d = class_d(c);
+        const int kc = class_kc(c);
+        const int hier = class_hier(c);
         const int split = mq > 1 ? 1 : choose_split(tn, all_units, cus, kc);
         // the matrix-core kernel runs one wavefront per query tile
         const int xf = (xf_pref == 2 && (split > 1 || mq > 1)) ? 1 : xf_pref;
@@ -347,10 +377,10 @@ int launch_joins(const Meta& meta, const std::vector<ClassPlan>& plans, const Tu
         a.split = split;
         a.mq = mq;
         a.stats = tn.stats;
-        const int per_cu = join_blocks_per_cu(d, kc, xf, split, mq);
+        const int per_cu = join_blocks_per_cu(d, kc, xf, hier, split, mq);
         if (per_cu <= 0) return fail(SNAPS_EDEVICE, "no occupancy for join kernel d=%d kc=%d split=%d", d, kc, split);
         int grid = std::min<int64_t>((int64_t)per_cu * cus, p.units);
-        hipError_t e = launch_join(d, kc, xf, a, grid, s);
+        hipError_t e = launch_join(d, kc, xf, hier, a, grid, s);
         if (e != hipSuccess) return hip_fail(e, "join kernel launch");
     }
     return SNAPS_OK;
@@ -376,6 +406,7 @@ struct RunJob {
     int64_t pair_cap;
     int32_t mode;           // per-job overrides of the call's tuning (0: none)
     int32_t index_dims;
+    int32_t tile_shape;
 };
 
 void count_large(const std::vector<RunJob>& jobs, int* n_large, int* n_lrank) {
@@ -424,6 +455,7 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
     meta.order = reinterpret_cast<int32_t*>(base + ml.order);
     meta.unit_prefix = reinterpret_cast<int32_t*>(base + ml.unit_prefix);
     meta.tile_prefix = reinterpret_cast<int32_t*>(base + ml.tile_prefix);
+    meta.super_prefix = reinterpret_cast<int32_t*>(base + ml.super_prefix);
     meta.counters = reinterpret_cast<int32_t*>(base + ml.counters);
     meta.n_counters = kNumClasses * kQueues;
 
@@ -432,12 +464,15 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
     size_t off = ml.bytes;
     int64_t total_tiles = 0;
     std::vector<int32_t> tile_prefix(n_jobs + 1, 0);
+    std::vector<int32_t> super_prefix(n_jobs + 1, 0);
+    int64_t total_supers = 0;
     for (int i = 0; i < n_jobs; ++i) {
         const RunJob& r = jobs[i];
         job_base[i] = base + off;
         Tune tj = tn;
         if (r.mode > 0) tj.mode = r.mode;
         if (r.index_dims > 0) tj.index_dims = r.index_dims;
+        if (r.tile_shape > 0) tj.tile_shape = r.tile_shape;
         DevJob j = make_devjob(r.pop, r.mask, r.plan, r.eps, tj, base + off);
         j.eps_count = r.eps_count;
         j.eps_mean = r.eps_mean;
@@ -456,13 +491,19 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         total_tiles += r.plan.ntiles;
         if (total_tiles > INT32_MAX / 2) return fail(SNAPS_EUNSUPPORTED, "too many tiles in one call");
         tile_prefix[i + 1] = (int32_t)total_tiles;
+        total_supers += r.plan.nsuper;
+        super_prefix[i + 1] = (int32_t)total_supers;
     }
 
     // Group jobs into kernel classes (dimensionality, top-k capacity); within
     // a class, the most expensive jobs (largest n) first, dealt round-robin
     // over the per-XCD queues.
     std::vector<std::vector<int>> members(kNumClasses);
-    for (int i = 0; i < n_jobs; ++i) members[class_id(jobs[i].plan.d, jobs[i].plan.kc)].push_back(i);
+    std::vector<int> job_class(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        job_class[i] = class_id(jobs[i].plan.d, jobs[i].plan.kc, table[i].hier);
+        members[job_class[i]].push_back(i);
+    }
     int64_t units1 = 0;
     for (int i = 0; i < n_jobs; ++i) {
         const int ql = join_ql(jobs[i].plan.kc);
@@ -480,8 +521,7 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         ClassPlan& p = plans[c];
         p.count = (int)m.size();
         if (p.count == 0) continue;
-        static const int kKcOf[5] = {0, 5, 10, 20, 32};
-        const int per_unit = join_ql(kKcOf[c % 5]) * mq;      // query tiles per work unit
+        const int per_unit = join_ql(class_kc(c)) * mq;      // query tiles per work unit
         for (int q = 0; q < kQueues; ++q) {
             p.q_order_off[q] = (int)order.size();
             p.q_prefix_off[q] = (int)unit_prefix.size();
@@ -572,9 +612,10 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
             ia.meta = meta;
             ia.n_jobs = 1;
             ia.seed = 1;
-            const ClassPlan& p = plans[class_id(jobs[0].plan.d, jobs[0].plan.kc)];
+            const ClassPlan& p = plans[job_class[0]];
             ia.single_units = p.q_units[0];
             ia.single_tiles = table[0].ntiles;
+            ia.single_supers = table[0].nsuper;
             ia.single = table[0];
             e = launch_index_sort(ia, 1, s);
             if (e != hipSuccess) return hip_fail(e, "index sort launch");
@@ -591,6 +632,7 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         put(ml.order, order.data(), order.size() * sizeof(int32_t));
         put(ml.unit_prefix, unit_prefix.data(), unit_prefix.size() * sizeof(int32_t));
         put(ml.tile_prefix, tile_prefix.data(), tile_prefix.size() * sizeof(int32_t));
+        put(ml.super_prefix, super_prefix.data(), super_prefix.size() * sizeof(int32_t));
         put(ml.li, lidx.data(), lidx.size() * sizeof(LargeIndex));
         put(ml.iseg, iseg.data(), iseg.size() * sizeof(SortSeg));
         put(ml.ichunk, ichunk.data(), ichunk.size() * sizeof(int32_t));
@@ -619,6 +661,8 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
     if (do_index) {
         e = launch_reorder(meta, n_jobs, (int32_t)total_tiles, s);
         if (e != hipSuccess) return hip_fail(e, "reorder launch");
+        e = launch_super_boxes(meta, n_jobs, (int32_t)total_supers, s);
+        if (e != hipSuccess) return hip_fail(e, "super-tile boxes launch");
     }
     if (do_join) {
         e = launch_zero_indeg(meta, n_jobs, (int32_t)total_tiles, s);
@@ -708,8 +752,11 @@ static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, const snaps_tunin
         if (j.mode < 0 || j.mode > 2) return fail(SNAPS_EINVAL, "job %d: mode must be 0, 1 or 2", i);
         if (j.index_dims < 0 || j.index_dims > kMaxIndexDims)
             return fail(SNAPS_EINVAL, "job %d: index_dims must be in [0, %d]", i, kMaxIndexDims);
+        if (j.tile_shape < 0 || j.tile_shape > 3) return fail(SNAPS_EINVAL, "job %d: tile_shape must be 0, 1, 2 or 3", i);
+        if (j.reserved != 0) return fail(SNAPS_EINVAL, "job %d: reserved must be zero", i);
         r.mode = j.mode;
         r.index_dims = j.index_dims;
+        r.tile_shape = j.tile_shape;
         if (j.knn_dist && !j.knn_ids) return fail(SNAPS_EINVAL, "job %d: knn_dist needs knn_ids", i);
         r.knn_ids = j.knn_ids;
         r.knn_dist = j.knn_dist;
@@ -984,7 +1031,6 @@ int snaps_outlier_scores_static(const snaps_job* jobs, int32_t n_jobs, const sna
     if (rc != SNAPS_OK) return rc;
     return run(rj, resolve_tune(tune), ws, SNAPS_STATIC_SCRATCH_BYTES, static_cast<hipStream_t>(stream));
 }
-
 
 // ------------------------------------------------------------------ serving
 

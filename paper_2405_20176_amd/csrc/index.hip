@@ -42,6 +42,8 @@ __global__ __launch_bounds__(kSortThreads) void k_index_sort(IndexArgs A) {
             A.meta.unit_prefix[1] = A.single_units;
             A.meta.tile_prefix[0] = 0;
             A.meta.tile_prefix[1] = A.single_tiles;
+            A.meta.super_prefix[0] = 0;
+            A.meta.super_prefix[1] = A.single_supers;
         }
     } else {
         J = A.meta.table[blockIdx.x];
@@ -129,6 +131,7 @@ __global__ __launch_bounds__(64) void k_reorder(Meta m, int32_t n_jobs) {
     __shared__ float s_tile[kTile * row_stride(kMaxD)];
     float* row = s_tile + lane * dp;
     float* box = J.boxes + (int64_t)t * 2 * dp;
+    float* hbox = J.hboxes + (int64_t)t * 4 * dp;
     int id = INT32_MAX;
     if (valid) id = J.perm[pos];
     else J.perm[pos] = INT32_MAX;
@@ -141,12 +144,17 @@ __global__ __launch_bounds__(64) void k_reorder(Meta m, int32_t n_jobs) {
             if (f < d) {
                 v = valid ? J.cols[(int64_t)J.feat[f] * J.ld + id] : qnan;
                 if (valid) norm = fmaf(v, v, norm);
-                const float mn = wave_min(valid ? v : INFINITY);
-                const float mx = wave_max(valid ? v : -INFINITY);
+                // corners of each 32-object half, then of the whole tile
+                const float hmn = half_min(valid ? v : INFINITY);
+                const float hmx = half_max(valid ? v : -INFINITY);
+                const float mn = fminf(hmn, __shfl_xor(hmn, 32, 64));
+                const float mx = fmaxf(hmx, __shfl_xor(hmx, 32, 64));
                 if (lane == 0) { box[f] = mn; box[dp + f] = mx; }
+                if ((lane & 31) == 0) { hbox[(lane >> 5) * 2 * dp + f] = hmn; hbox[(lane >> 5) * 2 * dp + dp + f] = hmx; }
             } else {
                 v = 0.f;
                 if (lane == 0) { box[f] = 0.f; box[dp + f] = 0.f; }
+                if ((lane & 31) == 0) { hbox[(lane >> 5) * 2 * dp + f] = 0.f; hbox[(lane >> 5) * 2 * dp + dp + f] = 0.f; }
             }
             row[f] = v;
         }
@@ -160,6 +168,36 @@ __global__ __launch_bounds__(64) void k_reorder(Meta m, int32_t n_jobs) {
     __syncthreads();
     float* span = J.xs + (int64_t)t * kTile * dp;
     for (int i = lane; i < kTile * dp; i += kTile) span[i] = s_tile[i];
+}
+
+// Corners of each super-tile (kSuper consecutive tiles of one job): one
+// wavefront per super-tile, one lane per tile, after k_reorder.
+__global__ __launch_bounds__(64) void k_super_boxes(Meta m, int32_t n_jobs) {
+    const int u = blockIdx.x;
+    int lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (m.super_prefix[mid] <= u) lo = mid; else hi = mid;
+    }
+    const DevJob J = m.table[lo];
+    const int S = u - m.super_prefix[lo];
+    const int t = S * kSuper + (int)threadIdx.x;
+    const bool valid = t < J.ntiles;
+    const int dp = row_stride(J.d);
+    for (int f = 0; f < dp; ++f) {
+        const float l = wave_min(valid ? J.boxes[((int64_t)t * 2) * dp + f] : INFINITY);
+        const float h = wave_max(valid ? J.boxes[((int64_t)t * 2 + 1) * dp + f] : -INFINITY);
+        if (threadIdx.x == 0) {
+            J.sboxes[((int64_t)S * 2) * dp + f] = l;
+            J.sboxes[((int64_t)S * 2 + 1) * dp + f] = h;
+        }
+    }
+}
+
+hipError_t launch_super_boxes(const Meta& m, int32_t n_jobs, int32_t total_supers, hipStream_t s) {
+    if (total_supers <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_super_boxes, dim3(total_supers), dim3(64), 0, s, m, n_jobs);
+    return hipGetLastError();
 }
 
 // Clears the in-degree outputs of every job (four 64-object tiles per

@@ -23,11 +23,13 @@ size_t join_lds_bytes(int kc, int split) {
 
 namespace {
 
-// xf: 0 direct form, 1 vector-ALU prefilter, 2 matrix-core prefilter.
-JoinFn pick(int D, int kc, int xf) {
+// xf: 0 direct form, 1 vector-ALU prefilter, 2 matrix-core prefilter;
+// hier: the matrix-core kernel's walk with super-tile and candidate-half
+// culls (the vector-ALU kernels have one walk).
+JoinFn pick(int D, int kc, int xf, int hier) {
     if (xf == 2) {
-        if (D >= 2 && D <= 8) return join_mfma_pick_group0(D, kc);
-        if (D >= 9 && D <= 16) return join_mfma_pick_group1(D, kc);
+        if (D >= 2 && D <= 8) return hier ? join_mfma_pick_group2(D, kc) : join_mfma_pick_group0(D, kc);
+        if (D >= 9 && D <= 16) return hier ? join_mfma_pick_group3(D, kc) : join_mfma_pick_group1(D, kc);
         return nullptr;
     }
     if (D >= 2 && D <= 6) return join_pick_group0(D, kc, xf);
@@ -39,8 +41,8 @@ JoinFn pick(int D, int kc, int xf) {
 
 }  // namespace
 
-int join_blocks_per_cu(int D, int kc, int xf, int split, int mq) {
-    JoinFn fn = pick(D, kc, xf);
+int join_blocks_per_cu(int D, int kc, int xf, int hier, int split, int mq) {
+    JoinFn fn = pick(D, kc, xf, hier);
     if (!fn) return 0;
     int nb = 0;
     const int threads = 64 * (split > mq ? split : mq);
@@ -50,8 +52,8 @@ int join_blocks_per_cu(int D, int kc, int xf, int split, int mq) {
     return nb;
 }
 
-hipError_t launch_join(int D, int kc, int xf, const JoinArgs& a, int grid, hipStream_t s) {
-    JoinFn fn = pick(D, kc, xf);
+hipError_t launch_join(int D, int kc, int xf, int hier, const JoinArgs& a, int grid, hipStream_t s) {
+    JoinFn fn = pick(D, kc, xf, hier);
     if (!fn) return hipErrorInvalidValue;
     JoinArgs copy = a;
     void* args[] = {&copy};

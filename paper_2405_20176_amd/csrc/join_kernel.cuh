@@ -83,14 +83,17 @@ __device__ __forceinline__ float xf_limit(float qn, float thr, float cq) {
     return fmaf(-cq, qn + thr, 0.5f * (qn - thr));
 }
 
-// Tile visited at step s of a walk that starts at t0 and alternates outward
-// (t0, t0+1, t0-1, t0+2, ...) modulo nt: a bijection of [0, nt).
-__device__ __forceinline__ int spiral(int t0, int s, int nt) {
-    const int off = (s & 1) ? ((s + 1) >> 1) : -(s >> 1);
-    int t = t0 + off;
-    t %= nt;
-    if (t < 0) t += nt;
-    return t;
+// Tile visited at step s of the candidate walk of query tile t0 over nt
+// tiles: tiles in order of their index distance from t0, the higher one
+// first at equal distance, and once one end is reached the other side alone
+// (t0, t0+1, t0-1, t0+2, t0-2, ...).  A bijection of [0, nt).  The join on
+// the matrix cores walks the same order as a merge of its two frontiers and
+// can drop a whole super-tile of kSuper tiles when a frontier enters it, so
+// the tiles it visits keep this relative order.
+__device__ __forceinline__ int walk_tile(int t0, int s, int nt) {
+    const int m = min(t0, nt - 1 - t0);
+    if (s <= 2 * m) return t0 + ((s & 1) ? ((s + 1) >> 1) : -(s >> 1));
+    return t0 < nt - 1 - t0 ? t0 + s - m : t0 + m - s;
 }
 
 // Candidates per group of the distance loop: the group's rows are loaded
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
 
         for (int s = (W > 1 ? 0 : wave); s < nt; s += (W > 1 ? 1 : S)) {
             if (W > 1 && s > 0) __syncthreads();             // keep the wavefronts in lockstep
-            const int t = spiral(W > 1 ? tu : t0, s, nt);
+            const int t = walk_tile(W > 1 ? tu : t0, s, nt);
             if (prune) {
                 cptr<float> bx = boxes + (int64_t)t * 2 * DP;
                 bool near = false;

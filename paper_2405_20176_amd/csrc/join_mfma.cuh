@@ -30,6 +30,19 @@
 // are identical to both k_join flavours.  (A wavefront-uniform walk over the
 // union of the masks costs one iteration per distinct candidate; the
 // per-lane walk costs the largest per-query count.)
+//
+// Two walks (template parameter H).  H = 0 visits the candidate tiles in the
+// order of walk_tile and skips a tile whose box no query can reach; the
+// contraction of a 32-query block row that no query of it can reach is
+// skipped.  H = 1 adds two levels: a frontier of the walk that enters a new
+// super-tile (kSuper tiles) first tests the super-tile's box and drops all
+// of its tiles on that side if no query can reach it, and, for jobs that ask
+// for it, each candidate tile is tested as two 32-object halves with boxes
+// of their own, so each of the four 32 x 32 blocks of a tile pair is
+// contracted only if a query of its row block may reach its half.  The tiles
+// H = 1 visits keep the order of walk_tile.  Both give the same results; they
+// differ in the work skipped and in register use (H = 0 keeps the leaner
+// kernel for the jobs whose index gains nothing from the extra levels).
 #pragma once
 
 #include "join_kernel.cuh"
@@ -51,7 +64,7 @@ __device__ __forceinline__ constexpr int acc_row(int rb, int r, int h) {
 
 }  // namespace mfma_detail
 
-template <int D, int KC>
+template <int D, int KC, int H>
 __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
     using namespace mfma_detail;
     constexpr int DP = row_stride(D);
@@ -67,7 +80,10 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
     __shared__ int s_unit, s_queue;
     __shared__ uint2 s_mask[64];            // per-query candidate masks of one tile pair
     __shared__ __align__(16) float s_cand[64][DP];   // candidate rows of a tile pair with passes
-    constexpr int kRowShift = 28;           // walk entries: tile index | reachable block rows << 28
+    // Walk entries: tile index | the 32 x 32 blocks (query block row rb,
+    // candidate half cb) that may hold a pair in reach, bit rb + 2 cb, << 26
+    // (H = 0 sets both halves of a block row together).
+    constexpr int kRowShift = 26;
     constexpr int kTileMask = (1 << kRowShift) - 1;
 
     const int lane = threadIdx.x;
@@ -174,31 +190,84 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
             return false;
         };
 
-        // Next candidate tile of the walk whose box may hold a candidate
-        // (or -1 at the end); advances the walk position ws.  Bits 28-29 of
-        // the result flag the 32-query block rows with a query that may reach
-        // the box (the other block row's contraction is skipped).
-        int ws = 0;
-        auto next_tile = [&]() -> int {
-            while (ws < nt) {
-                const int t = spiral(t0, ws, nt);
-                ++ws;
-                if (!prune) return t | (3 << kRowShift);
-                cptr<float> bx = boxes + (int64_t)t * 2 * DP;
-                float lb = 0.f;
+        // Next candidate tile of the walk whose box may hold a candidate (or
+        // -1 at the end), in the order of walk_tile; bits 26-29 of the result
+        // flag the 32 x 32 blocks with a query that may reach the candidates
+        // (the other blocks' contractions are skipped).
+        auto reach_of = [&](cptr<float> bx) -> unsigned long long {
+            float lb = 0.f;
 #pragma unroll
-                for (int f = 0; f < D; ++f) {
-                    const float g = fmaxf(fmaxf(bx[f] - q[f], q[f] - bx[DP + f]), 0.f);
-                    lb = fmaf(g, g, lb);
-                }
-                const unsigned long long reach = __ballot(lb <= thr);
-                if (reach) {
-                    const int rows = ((unsigned)reach ? 1 : 0) | ((reach >> 32) ? 2 : 0);
-                    return t | (rows << kRowShift);
-                }
-                ++skipped;
+            for (int f = 0; f < D; ++f) {
+                const float g = fmaxf(fmaxf(bx[f] - q[f], q[f] - bx[DP + f]), 0.f);
+                lb = fmaf(g, g, lb);
             }
-            return -1;
+            return __ballot(lb <= thr);
+        };
+        int ws = 0;                                  // H = 0: walk step
+        // H = 1: the walk as a merge of its two frontiers (the tile nearer to
+        // t0, the right one on ties), each with the super-tile it is in.
+        int wr = t0, wl = t0 - 1;
+        int sr = t0 / kSuper, sl = t0 / kSuper;
+        cptr<float> sboxes = as_const((const float*)Jp->sboxes);
+        cptr<float> hboxes = as_const((const float*)Jp->hboxes);
+        const int halves = H ? Jp->halves : 0;
+        auto next_tile = [&]() -> int {
+            if constexpr (H == 0) {
+                while (ws < nt) {
+                    const int t = walk_tile(t0, ws, nt);
+                    ++ws;
+                    if (!prune) return t | (15 << kRowShift);
+                    const unsigned long long reach = reach_of(boxes + (int64_t)t * 2 * DP);
+                    if (reach) {
+                        const int rows = ((unsigned)reach ? 1 : 0) | ((reach >> 32) ? 2 : 0);
+                        return t | ((rows | (rows << 2)) << kRowShift);
+                    }
+                    ++skipped;
+                }
+                return -1;
+            } else {
+                for (;;) {
+                    const bool rv = wr < nt, lv = wl >= 0;
+                    if (!rv && !lv) return -1;
+                    int t;
+                    if (rv && (!lv || wr - t0 <= t0 - wl)) {
+                        if (prune && wr / kSuper != sr) {
+                            sr = wr / kSuper;
+                            if (!reach_of(sboxes + (int64_t)sr * 2 * DP)) {
+                                const int e = min(nt, (sr + 1) * kSuper);
+                                skipped += e - wr;
+                                wr = e;
+                                continue;
+                            }
+                        }
+                        t = wr++;
+                    } else {
+                        if (prune && wl / kSuper != sl) {
+                            sl = wl / kSuper;
+                            if (!reach_of(sboxes + (int64_t)sl * 2 * DP)) {
+                                skipped += wl - sl * kSuper + 1;
+                                wl = sl * kSuper - 1;
+                                continue;
+                            }
+                        }
+                        t = wl--;
+                    }
+                    if (!prune) return t | (15 << kRowShift);
+                    int blocks;
+                    if (halves) {
+                        const unsigned long long r0 = reach_of(hboxes + (int64_t)t * 4 * DP);
+                        const unsigned long long r1 = reach_of(hboxes + (int64_t)t * 4 * DP + 2 * DP);
+                        blocks = ((unsigned)r0 ? 1 : 0) | ((r0 >> 32) ? 2 : 0) | ((unsigned)r1 ? 4 : 0) |
+                                 ((r1 >> 32) ? 8 : 0);
+                    } else {
+                        const unsigned long long r = reach_of(boxes + (int64_t)t * 2 * DP);
+                        const int rows = ((unsigned)r ? 1 : 0) | ((r >> 32) ? 2 : 0);
+                        blocks = rows | (rows << 2);
+                    }
+                    if (blocks) return t | (blocks << kRowShift);
+                    ++skipped;
+                }
+            }
         };
         // Raw B operands of tile t (candidate rows 32 cb + col: lane half 0
         // reads the even dimensions, half 1 the odd ones, then h), loaded
@@ -227,10 +296,18 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
         // tile's loads are waited on only when that tile is screened).
         auto process = [&](int tv, float (&br)[2][KSTEPS + 2]) {
             const int t = tv & kTileMask;
-            const int rows = tv >> kRowShift;
+            const int blocks = tv >> kRowShift;
+            const int rows = (blocks | (blocks >> 2)) & 3;
             ++scanned;
-            pairs += (long long)((rows & 1 ? min(nq, 32) : 0) + (rows & 2 ? max(0, nq - 32) : 0)) *
-                     min(kTile, n - t * kTile);
+            if constexpr (H == 0) {
+                pairs += (long long)((rows & 1 ? min(nq, 32) : 0) + (rows & 2 ? max(0, nq - 32) : 0)) *
+                         min(kTile, n - t * kTile);
+            } else {
+                const int nq0 = min(nq, 32), nq1 = max(0, nq - 32);
+                const int nc0 = max(0, min(32, n - t * kTile)), nc1 = max(0, min(32, n - t * kTile - 32));
+                pairs += ((blocks & 1 ? nq0 : 0) + (blocks & 2 ? nq1 : 0)) * nc0 +
+                         ((blocks & 4 ? nq0 : 0) + (blocks & 8 ? nq1 : 0)) * nc1;
+            }
             const int cbase = t * kTile;
 
             // B operands in place: 0 in the pad slot of an odd d, then (1, h)
@@ -253,13 +330,29 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
                 if (!((rows >> rb) & 1)) continue;
+                // H = 1: a candidate half out of reach of this block row is
+                // not contracted (both chains otherwise, interleaved on the
+                // matrix pipe); its scores never pass.
+                const bool act0 = H ? ((blocks >> rb) & 1) != 0 : true;
+                const bool act1 = H ? ((blocks >> (rb + 2)) & 1) != 0 : true;
                 f16v acc[2];
+                if (act0 && act1) {
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
-                    acc[cb] = f16v{};
+                    for (int cb = 0; cb < 2; ++cb) {
+                        acc[cb] = f16v{};
+#pragma unroll
+                        for (int s2 = 0; s2 < NSTEP; ++s2)
+                            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][s2], br[cb][s2], acc[cb], 0, 0, 0);
+                    }
+                } else {
+                    const int cb = act0 ? 0 : 1;
+                    acc[0] = f16v{};
+                    acc[1] = f16v{};
+                    f16v a1 = f16v{};
 #pragma unroll
                     for (int s2 = 0; s2 < NSTEP; ++s2)
-                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][s2], br[cb][s2], acc[cb], 0, 0, 0);
+                        a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][s2], cb ? br[1][s2] : br[0][s2], a1, 0, 0, 0);
+                    if (cb) acc[1] = a1; else acc[0] = a1;
                 }
                 float mx0 = -INFINITY, mx1 = -INFINITY;     // NaN pads never pass
 #pragma unroll
@@ -267,11 +360,13 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
                     mx0 = fmaxf(mx0, acc[0][r]);
                     mx1 = fmaxf(mx1, acc[1][r]);
                 }
+                if (!act0) mx0 = -INFINITY;
+                if (!act1) mx1 = -INFINITY;
                 if (!__any(mx0 >= nh0 || mx1 >= nh1)) continue;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const unsigned long long b0 = __ballot(acc[0][r] >= nh0);
-                    const unsigned long long b1 = __ballot(acc[1][r] >= nh1);
+                    const unsigned long long b0 = act0 ? __ballot(acc[0][r] >= nh0) : 0ull;
+                    const unsigned long long b1 = act1 ? __ballot(acc[1][r] >= nh1) : 0ull;
                     if (b0 | b1) {
                         const int i0 = acc_row(rb, r, 0);
                         if (lane == 0) {
@@ -375,35 +470,37 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
     }
 }
 
-template <int D, int KC>
+template <int D, int KC, int H>
 __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
-    join_mfma_body<D, KC>(A);
+    join_mfma_body<D, KC, H>(A);
 }
 
 // The same kernel held to 128 VGPRs, four wavefronts per SIMD instead of
 // three.  It spills a few registers; for d = 7..10 with k <= 10 it is still
 // 2-10 % faster (measured per d over 1,024 SNAPShot1-shaped subspaces), at
 // d >= 11 it is slower.
-template <int D, int KC>
+template <int D, int KC, int H>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_join_mfma_w4(JoinArgs A) {
-    join_mfma_body<D, KC>(A);
+    join_mfma_body<D, KC, H>(A);
 }
 
-template <int D>
+template <int D, int H>
 JoinFn join_mfma_pick_kc(int kc) {
     constexpr bool w4 = D >= 7 && D <= 10;
     switch (kc) {
-        case 0: return k_join_mfma<D, 0>;
-        case 5: return w4 ? k_join_mfma_w4<D, 5> : k_join_mfma<D, 5>;
-        case 10: return w4 ? k_join_mfma_w4<D, 10> : k_join_mfma<D, 10>;
-        case 20: return k_join_mfma<D, 20>;
-        case 32: return k_join_mfma<D, 32>;
+        case 0: return k_join_mfma<D, 0, H>;
+        case 5: return w4 ? k_join_mfma_w4<D, 5, H> : k_join_mfma<D, 5, H>;
+        case 10: return w4 ? k_join_mfma_w4<D, 10, H> : k_join_mfma<D, 10, H>;
+        case 20: return k_join_mfma<D, 20, H>;
+        case 32: return k_join_mfma<D, 32, H>;
     }
     return nullptr;
 }
 
 // Instantiation groups, one per translation unit.
-JoinFn join_mfma_pick_group0(int D, int kc);
-JoinFn join_mfma_pick_group1(int D, int kc);
+JoinFn join_mfma_pick_group0(int D, int kc);    // d 2..8, H = 0
+JoinFn join_mfma_pick_group1(int D, int kc);    // d 9..16, H = 0
+JoinFn join_mfma_pick_group2(int D, int kc);    // d 2..8, H = 1
+JoinFn join_mfma_pick_group3(int D, int kc);    // d 9..16, H = 1
 
 }  // namespace snaps

@@ -8,6 +8,7 @@
 namespace snaps {
 
 constexpr int kTile = 64;            // objects per tile (= one wavefront of queries)
+constexpr int kSuper = 64;           // tiles per super-tile (the join culls these first)
 constexpr int kMaxD = 16;            // largest subspace dimensionality
 constexpr int kMaxIndexDims = 6;     // c <= 6 indexed dimensions (paper Sec. 3.8.1)
 constexpr int kLdsSortMax = 32768;   // largest n sorted inside one workgroup's LDS
@@ -45,6 +46,12 @@ struct DevJob {
     int32_t* perm;           // [ntiles*64] index position -> object id (pads: INT32_MAX)
                              // (the id is also stored in slot d + 1 of each xs row)
     float* boxes;            // [ntiles][2][row_stride(d)] per-tile lower / upper corners
+    float* sboxes;           // [nsuper][2][row_stride(d)] corners of each run of kSuper tiles
+    float* hboxes;           // [ntiles][2 halves][2][row_stride(d)] corners of objects 0-31 and 32-63 of each tile
+    int32_t nsuper;          // ceil(ntiles / kSuper)
+    int32_t halves;          // 1: the join culls 32-candidate halves of a tile by their own boxes
+    int32_t hier;            // 1: joined by the walk with super-tile culls (kernel variant, host side)
+    int32_t pad_h;
     int32_t* eps_count;      // outputs, [n], indexed by object id (may be null)
     float* eps_mean;
     int32_t* indeg;
@@ -65,6 +72,7 @@ struct Meta {
     int32_t* order;          // join processing order, grouped by kernel class
     int32_t* unit_prefix;    // per class: tiles prefix over that class's jobs (n+1 entries each)
     int32_t* tile_prefix;    // [n_jobs + 1] tiles prefix in table order
+    int32_t* super_prefix;   // [n_jobs + 1] super-tiles prefix in table order
     int32_t* counters;       // [n_classes * kQueues] persistent work counters
     int32_t n_counters;
 };
@@ -75,6 +83,7 @@ struct IndexArgs {
     int32_t seed;            // 1: single job passed by value, block 0 writes the metadata
     int32_t single_units;    // join work units of the single job
     int32_t single_tiles;    // tiles of the single job
+    int32_t single_supers;   // super-tiles of the single job
     DevJob single;
 };
 
@@ -251,6 +260,8 @@ __host__ __device__ constexpr int join_ql(int kc) { return kc < 0 ? 2 : 1; }
 // Launchers (each returns the HIP status of the launch).
 hipError_t launch_index_sort(const IndexArgs& a, int grid, hipStream_t s);
 hipError_t launch_reorder(const Meta& m, int32_t n_jobs, int32_t total_tiles, hipStream_t s);
+// Corners of every super-tile of every job (after the reorder).
+hipError_t launch_super_boxes(const Meta& m, int32_t n_jobs, int32_t total_supers, hipStream_t s);
 hipError_t launch_rank(const RankArgs& a, hipStream_t s);
 hipError_t launch_grid_join(const GridJob* jobs, const int32_t* tile_prefix, int n_jobs, int total_tiles, int d,
                             hipStream_t s);
@@ -287,10 +298,11 @@ hipError_t launch_large_index(const DevJob* table, const LargeIndex* li, int n_l
 hipError_t launch_large_rank(const DevJob* table, const LargeRank* lr, int n_large, const int32_t* chunk_prefix,
                              int total_chunks, const SortSeg* segs, const int32_t* seg_chunk_prefix,
                              int total_seg_chunks, hipStream_t s);
-// Join kernel for dimensionality D, top-k capacity class kc and filter
-// flavour xf; grid == 0 asks for a persistent grid filling the device.
-hipError_t launch_join(int D, int kc, int xf, const JoinArgs& a, int grid, hipStream_t s);
-int join_blocks_per_cu(int D, int kc, int xf, int split, int mq);
+// Join kernel for dimensionality D, top-k capacity class kc, filter
+// flavour xf and walk (hier: super-tile and candidate-half culls of the
+// matrix-core kernel); grid == 0 asks for a persistent grid filling the device.
+hipError_t launch_join(int D, int kc, int xf, int hier, const JoinArgs& a, int grid, hipStream_t s);
+int join_blocks_per_cu(int D, int kc, int xf, int hier, int split, int mq);
 int kc_class(int k);              // top-k capacity used for a k (0 for no kNN)
 size_t join_lds_bytes(int kc, int split);
 

@@ -179,6 +179,31 @@ class Batcher:
         return np.array([r.done - r.arrival for r in self.finished if r.status == "done"])
 
 
+def serve_serial(executor, requests: Sequence[Request], open_loop: bool = True,
+                 clock: Callable[[], float] = time.perf_counter) -> List[Request]:
+    """The plain form of serving, for comparison: one request at a time, in
+    arrival order, each launched alone and waited for before the next one
+    starts (no batching, no overlap).  With ``open_loop`` a request is not
+    started before its arrival time (seconds after the start); otherwise all
+    are taken as arrived at the start.  Returns the finished requests."""
+    t0 = clock()
+    out = []
+    for r in sorted(requests, key=lambda q: q.arrival):
+        if open_loop:
+            while clock() - t0 < r.arrival:
+                time.sleep(min(0.001, max(0.0, r.arrival - (clock() - t0))))
+            r.arrival += t0
+        else:
+            r.arrival = t0
+        r.admitted = clock()
+        h = executor.launch([r])
+        r.result = executor.finish(h)[0]
+        r.done = clock()
+        r.status = "done"
+        out.append(r)
+    return out
+
+
 class GpuExecutor:
     """Executor over libsnaps: one stream per in-flight batch slot; alerts go
     up from pinned host buffers and results come back the same way."""

@@ -47,13 +47,14 @@ class c_job(ctypes.Structure):
     _fields_ = [("pop", ctypes.POINTER(c_population)), ("mask", ctypes.c_uint32), ("k", ctypes.c_int32),
                 ("eps", ctypes.c_float), ("out", c_scores), ("rank", ctypes.c_void_p),
                 ("ensemble", ctypes.c_void_p), ("mode", ctypes.c_int32), ("index_dims", ctypes.c_int32),
-                ("knn_ids", ctypes.c_void_p), ("knn_dist", ctypes.c_void_p)]
+                ("knn_ids", ctypes.c_void_p), ("knn_dist", ctypes.c_void_p), ("tile_shape", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class c_tuning(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("split", ctypes.c_int32), ("index_dims", ctypes.c_int32),
                 ("filter", ctypes.c_int32), ("passes", ctypes.c_int32), ("mq", ctypes.c_int32),
-                ("index_sort", ctypes.c_int32), ("reserved", ctypes.c_int32), ("stats", ctypes.c_void_p)]
+                ("index_sort", ctypes.c_int32), ("tile_shape", ctypes.c_int32), ("stats", ctypes.c_void_p)]
 
 
 PASS_INDEX, PASS_JOIN, PASS_RANK = 1, 2, 4
@@ -191,13 +192,14 @@ class Population:
 
 
 def tuning(mode=0, split=0, index_dims=0, filter=0, passes=0, stats: Optional[torch.Tensor] = None,
-           mq=0, index_sort=0) -> c_tuning:
+           mq=0, index_sort=0, tile_shape=0) -> c_tuning:
     """Tuning record; ``stats`` is an optional int64 CUDA tensor of 4
     accumulated join counters (pairs evaluated, tiles scanned, tiles
     skipped, pairs x dimensionality)."""
     t = c_tuning()
     t.mode, t.split, t.index_dims, t.filter, t.passes, t.mq = mode, split, index_dims, filter, passes, mq
     t.index_sort = index_sort
+    t.tile_shape = tile_shape
     t.stats = None if stats is None else stats.data_ptr()
     return t
 
@@ -268,6 +270,7 @@ class Job:
     index_dims: int = 0
     knn_ids: Optional[torch.Tensor] = None   # [n, k] int32, the kNN lists the in-degree was counted from
     knn_dist: Optional[torch.Tensor] = None  # [n, k] float32
+    tile_shape: int = 0                      # per-job override of the call's tile shape (0: none)
 
     @classmethod
     def alloc(cls, pop: Population, mask: int, k: int, eps: float, with_rank: bool = True,
@@ -298,6 +301,7 @@ def _c_jobs(jobs: Sequence[Job]):
         arr[i].index_dims = j.index_dims
         arr[i].knn_ids = None if j.knn_ids is None else j.knn_ids.data_ptr()
         arr[i].knn_dist = None if j.knn_dist is None else j.knn_dist.data_ptr()
+        arr[i].tile_shape = j.tile_shape
     return arr
 
 
@@ -398,6 +402,7 @@ class JobTable:
         self.knn_dist = torch.empty(total_k, dtype=torch.float32, device=dev) if with_lists else None
         self.mode = [0] * nj
         self.index_dims = [0] * nj
+        self.tile_shape = [0] * nj
         self.arr = (c_job * nj)()
         self._pops = {}
         for i, (pop, mask, k, eps) in enumerate(self.specs):
@@ -422,20 +427,23 @@ class JobTable:
     def __len__(self):
         return len(self.specs)
 
-    def set_walk(self, i: int, mode: int, index_dims: int):
-        self.mode[i], self.index_dims[i] = int(mode), int(index_dims)
+    def set_walk(self, i: int, mode: int, index_dims: int, tile_shape: int = 0):
+        self.mode[i], self.index_dims[i], self.tile_shape[i] = int(mode), int(index_dims), int(tile_shape)
         self.arr[i].mode, self.arr[i].index_dims = int(mode), int(index_dims)
+        self.arr[i].tile_shape = int(tile_shape)
 
     def walk_specs(self):
-        """Lightweight per-job records (pop, mask, k, eps, mode, index_dims)
-        for the autotuner; ``apply_walk`` copies their settings back."""
+        """Lightweight per-job records (pop, mask, k, eps, mode, index_dims,
+        tile_shape) for the autotuner; ``apply_walk`` copies their settings
+        back."""
         from types import SimpleNamespace
-        return [SimpleNamespace(pop=p, mask=m, k=k, eps=e, mode=self.mode[i], index_dims=self.index_dims[i])
+        return [SimpleNamespace(pop=p, mask=m, k=k, eps=e, mode=self.mode[i], index_dims=self.index_dims[i],
+                                tile_shape=self.tile_shape[i])
                 for i, (p, m, k, e) in enumerate(self.specs)]
 
     def apply_walk(self, recs):
         for i, r in enumerate(recs):
-            self.set_walk(i, r.mode, r.index_dims)
+            self.set_walk(i, r.mode, r.index_dims, getattr(r, "tile_shape", 0))
 
     def c_ptr(self, start: int = 0):
         return ctypes.cast(ctypes.byref(self.arr, start * ctypes.sizeof(c_job)), ctypes.POINTER(c_job))

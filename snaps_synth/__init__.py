@@ -21,10 +21,13 @@ from .generators import (  # noqa: F401
     gen_c2,
     gen_c3_jobs,
     gen_c3_population,
+    gen_c3_projected,
+    load_c3_eps,
     gen_c4,
     all_masks,
     mask_features,
     load_c1_eps,
+    load_c2_eps,
     load_c4_eps,
     FEATURE_NAMES,
     to_soa,

@@ -233,6 +233,18 @@ def gen_c2(n: int = 5_000_000):
     return x, masks.astype(np.uint32), 10, 20
 
 
+def load_c2_eps(path: str | None = None):
+    """The stored float32 epsilon of every C2 space (target mean count 20),
+    aligned with the masks of :func:`gen_c2`.  Written by
+    ``make_eps_tables.py c2``."""
+    path = path or os.path.join(TABLE_DIR, "c2_eps.npz")
+    z = np.load(path, allow_pickle=False)
+    masks = np.concatenate([[np.uint32((1 << N_FEATURES) - 1)], all_masks(dmin=2, dmax=2)]).astype(np.uint32)
+    if not np.array_equal(z["masks"], masks):
+        raise ValueError("C2 epsilon table does not match the space order")
+    return z["eps"].astype(np.float32)
+
+
 # --------------------------------------------------- C3 (batched uneven) ---
 
 @dataclass
@@ -269,6 +281,78 @@ def gen_c3_population(job: C3Job, n: int | None = None) -> np.ndarray:
     raw = snapshot1_like_raw(rng, job.n if n is None else n)
     x, _, _ = normalize_minmax(raw)
     return x
+
+
+def gen_c3_projected(job: C3Job, n: int | None = None) -> np.ndarray:
+    """The job's population in its own subspace: normalised float32 [n, d],
+    the subspace's features in ascending order -- all a job reads of its
+    population.  Only those d features are drawn, each from a stream of its
+    own (spawned from the job's seed), with the distributions of
+    :func:`snapshot1_like_raw`: the four colour-like features are drawn
+    jointly (correlated) whenever one of them is in the subspace, and the
+    0.5 % tail outliers (1-3 of the 15 features each, moved to mean +/-
+    U(6, 10) sigma; the rotation period in log space) come from one more
+    stream, so that every job sees the same outlier rows and features
+    whatever its subspace.  Normalisation is per feature over the
+    population, as for the other workloads."""
+    n = job.n if n is None else n
+    feats = mask_features(job.mask)
+    kids = job.seed.spawn(N_FEATURES + 1)
+    raw = np.empty((n, len(feats)), dtype=np.float64)
+    colour = None
+    for c, f in enumerate(feats):
+        if 3 <= f <= 6:
+            if colour is None:
+                cov = np.full((4, 4), 0.6) + 0.4 * np.eye(4)
+                colour = 0.4 + 0.1 * (np.random.default_rng(kids[3]).standard_normal((n, 4)) @
+                                      np.linalg.cholesky(cov).T)
+            raw[:, c] = colour[:, f - 3]
+            continue
+        rng = np.random.default_rng(kids[f])
+        if f == 0:
+            raw[:, c] = rng.normal(_LOGNORM_MU, _LOGNORM_SIG, size=n)      # log period; exp below
+        elif f == 1:
+            raw[:, c] = rng.gamma(2.0, 0.15, size=n)
+        elif f == 2:
+            raw[:, c] = rng.normal(15.0, 1.5, size=n)
+        elif f == 7:
+            raw[:, c] = rng.uniform(2.1, 3.3, size=n)
+        elif f == 8:
+            raw[:, c] = rng.beta(2.0, 12.0, size=n)
+        elif f == 9:
+            raw[:, c] = rng.rayleigh(0.12, size=n)
+        else:
+            raw[:, c] = rng.standard_normal(n)
+    rng = np.random.default_rng(kids[N_FEATURES])
+    n_out = int(round(0.005 * n))
+    if n_out:
+        rows = rng.choice(n, size=n_out, replace=False)
+        nf = rng.integers(1, 4, size=n_out)
+        which = np.argsort(rng.random((n_out, N_FEATURES)), axis=1)[:, :3]
+        sign = np.where(rng.random((n_out, 3)) < 0.5, 1.0, -1.0)
+        mag = rng.uniform(6.0, 10.0, size=(n_out, 3))
+        col_of = {f: c for c, f in enumerate(feats)}
+        for t in range(3):
+            for r, f, sg, mg, keep in zip(rows, which[:, t], sign[:, t], mag[:, t], t < nf):
+                if keep and int(f) in col_of:
+                    mu, sd = _COL_MOMENTS[int(f)]
+                    raw[r, col_of[int(f)]] = mu + sg * mg * sd
+    if 0 in feats:
+        raw[:, 0] = np.exp(raw[:, 0])
+    x, _, _ = normalize_minmax(raw)
+    return x
+
+
+def load_c3_eps(path: str | None = None):
+    """The stored float32 epsilon of every C3 job (sampler target = the job's
+    k), aligned with :func:`gen_c3_jobs`.  Written by ``make_eps_tables.py
+    c3``."""
+    path = path or os.path.join(TABLE_DIR, "c3_eps.npz")
+    z = np.load(path, allow_pickle=False)
+    jobs = gen_c3_jobs(len(z["eps"]))
+    if not (np.array_equal(z["masks"], [j.mask for j in jobs]) and np.array_equal(z["n"], [j.n for j in jobs])):
+        raise ValueError("C3 epsilon table does not match the job list")
+    return z["eps"].astype(np.float32)
 
 
 # ------------------------------------------------------------ C4 (serve) ---

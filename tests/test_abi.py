@@ -117,12 +117,13 @@ def test_outlier_scores_validation(lib):
     t = c_tuning()
     t.split = 3
     assert lib.snaps_outlier_scores(ctypes.byref(job), 1, ctypes.byref(t), None, 0, None) == -1
-    for field, value in (("index_sort", 3), ("reserved", 1), ("filter", 4), ("mq", 3)):
+    for field, value in (("index_sort", 3), ("tile_shape", 4), ("tile_shape", -1), ("filter", 4), ("mq", 3)):
         t = c_tuning()
         setattr(t, field, value)
         assert lib.snaps_outlier_scores(ctypes.byref(job), 1, ctypes.byref(t), None, 0, None) == -1, field
     # per-job overrides of the walk: mode 0..2, index_dims 0..6
-    for field, value in (("mode", 3), ("mode", -1), ("index_dims", 7), ("index_dims", -1)):
+    for field, value in (("mode", 3), ("mode", -1), ("index_dims", 7), ("index_dims", -1), ("tile_shape", 4),
+                         ("tile_shape", -1), ("reserved", 1)):
         bj = c_job.from_buffer_copy(job)
         setattr(bj, field, value)
         assert lib.snaps_outlier_scores(ctypes.byref(bj), 1, None, None, 0, None) == -1, (field, value)

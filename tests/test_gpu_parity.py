@@ -883,8 +883,9 @@ def test_per_job_walk_settings_and_autotuner(S):
 
     def run(settings, jobs=None):
         jobs = jobs or [S.Job.alloc(pop, m, 10, e, with_lists=True) for m, e in zip(masks, epss)]
-        for j, (mo, c) in zip(jobs, settings):
-            j.mode, j.index_dims = mo, c
+        for j, st in zip(jobs, settings):
+            j.mode, j.index_dims = st[0], st[1]
+            j.tile_shape = st[2] if len(st) > 2 else 0
         S.snaps_outlier_scores(jobs, S.tuning(split=1))
         torch.cuda.synchronize()
         return [job_out(j) for j in jobs]
@@ -899,14 +900,71 @@ def test_per_job_walk_settings_and_autotuner(S):
 
     ref = run([(0, 0)] * 3)
     check_scores(ref[1], run_oracle(x, masks[1], 10, epss[1]), 10, epss[1], label="defaults d=7")
-    for setting in [(1, 0), (2, 2), (2, 3), (2, 6)]:
+    for setting in [(1, 0), (2, 2), (2, 3), (2, 6), (2, 2, 2), (2, 4, 3), (1, 0, 2)]:
         same(ref, run([setting] * 3), f"setting {setting}")
+    # super-tile culls and candidate halves only skip work no query can
+    # reach, in the same walk order: bit for bit the same
+    for c in (2, 4):
+        a = run([(2, c, 1)] * 3)
+        for shape in (2, 3):
+            b = run([(2, c, shape)] * 3)
+            for ra, rb in zip(a, b):
+                for key in ra:
+                    np.testing.assert_array_equal(ra[key], rb[key], err_msg=f"shape {shape} {key} c={c}")
     jobs = [S.Job.alloc(pop, m, 10, e) for m, e in zip(masks, epss)]
     table = AT.tune(jobs, sample=2, reps=1)
     assert set(table) == {AT.class_key(AT.job_class(j)) for j in jobs}
     for key, v in table.items():
         d = int(key[1:key.index("_")])
         assert (v["mode"], v["index_dims"]) in AT.candidates(d)
-        assert set(v["ms"]) == {f"{m},{c}" for m, c in AT.candidates(d)}
+        assert v["tile_shape"] in (AT.TILE_FULL, AT.TILE_HALVES, AT.TILE_SUPER)
+        plain_keys = {f"{m},{c}" for m, c in AT.candidates(d)}
+        assert plain_keys <= set(v["ms"])
+        extra = set(v["ms"]) - plain_keys
+        assert extra == ({f"{v['mode']},{v['index_dims']},{t}" for t in "hs"} if v["mode"] == AT.MODE_PRUNE
+                         else set())
     assert AT.apply(jobs, table) == 3
-    same(ref, run([(j.mode, j.index_dims) for j in jobs], jobs), "autotuned")
+    same(ref, run([(j.mode, j.index_dims, j.tile_shape) for j in jobs], jobs), "autotuned")
+
+
+# ----------------------------------------------- super-tile walk at large n
+
+@pytest.mark.parametrize("d", [2, 5])
+def test_super_tile_walk_and_candidate_halves_large_n(S, d):
+    """A population of 200,000 objects (49 super-tiles of 64 tiles): the
+    matrix-core join culls super-tiles, then tiles (or 32-candidate halves)
+    by their boxes, or walks tile by tile; the vector-ALU direct form walks
+    the same tile order tile by tile.  All give identical results, bit for
+    bit, and 64 seeded queries match the oracle."""
+    rng = np.random.default_rng(200 + d)
+    n, k = 200_000, 10
+    x = (rng.random((n, d)) ** 2).astype(np.float32)
+    eps = 0.004 if d == 2 else 0.05
+    mask = (1 << d) - 1
+    pop = S.Population.from_rows(x)
+    outs = {}
+    for name, tune in (("mfma", S.tuning(split=1, filter=3, tile_shape=3)),
+                       ("mfma_halves", S.tuning(split=1, filter=3, tile_shape=2)),
+                       ("mfma_lean", S.tuning(split=1, filter=3, tile_shape=1)),
+                       ("valu_direct", S.tuning(split=1, filter=1))):
+        job = S.Job.alloc(pop, mask, k, eps, with_lists=True)
+        st = torch.zeros(4, dtype=torch.int64, device="cuda")
+        tune.stats = st.data_ptr()
+        S.snaps_outlier_scores([job], tune)
+        torch.cuda.synchronize()
+        outs[name] = job_out(job)
+        outs[name]["stats"] = st.cpu().numpy()
+    for name in ("mfma_halves", "mfma_lean", "valu_direct"):
+        for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank", "knn_ids", "knn_dist"):
+            np.testing.assert_array_equal(outs["mfma"][key], outs[name][key], err_msg=f"{name} {key} d={d}")
+    # the super-tile level skips most tiles; halves evaluate no more pairs
+    if d == 2:
+        assert outs["mfma"]["stats"][2] > 10 * outs["mfma"]["stats"][1]
+    assert outs["mfma_halves"]["stats"][0] <= outs["mfma"]["stats"][0]
+    qs = np.sort(rng.choice(n, size=64, replace=False))
+    ora = C.join(x, k, eps, band=(eps * (1 - TAU), eps * (1 + TAU)), qids=qs)
+    g = outs["mfma"]
+    exempt = ora["band"] > 0
+    assert ((g["eps_count"][qs] == ora["eps_count"]) | exempt).all()
+    check_knn(g["knn_ids"][qs], g["knn_dist"][qs], ora, k, label=f"super-tile walk d={d}", row_ids=qs)
+    assert int(g["indeg"].astype(np.int64).sum()) == n * k
