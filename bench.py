@@ -197,8 +197,14 @@ def serve_bench(S, G, dev, seconds: float, warmup_s: float = 10.0, n_streams: in
 
 
 def _c3_gen(job):
+    """One C3 population as feature-major float32 columns [d, ld] (ld a
+    multiple of 64), built in the worker process."""
     import snaps_synth as G
-    return job.index, G.gen_c3_projected(job)
+    x = G.gen_c3_projected(job)
+    n, d = x.shape
+    cols = np.zeros((d, (n + 63) // 64 * 64), dtype=np.float32)
+    cols[:, :n] = x.T
+    return job.index, n, cols
 
 
 def c3_bench(S, G, lib, dev, stream, steps: int, warmup: int, autotune_sample: int, plain: bool):
@@ -220,8 +226,8 @@ def c3_bench(S, G, lib, dev, stream, steps: int, warmup: int, autotune_sample: i
     workers = max(1, min(16, os.cpu_count() or 4))
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
-        for idx, x in pool.imap_unordered(_c3_gen, jobs, chunksize=4):
-            pops[idx] = S.Population.from_rows(x, device=dev)
+        for idx, n, cols in pool.imap_unordered(_c3_gen, jobs, chunksize=4):
+            pops[idx] = S.Population(torch.from_numpy(cols).to(dev), n)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     ns = np.array([j.n for j in jobs], dtype=np.int64)
@@ -235,7 +241,7 @@ def c3_bench(S, G, lib, dev, stream, steps: int, warmup: int, autotune_sample: i
     if autotune_sample > 0:
         ta = time.perf_counter()
         recs = tab.walk_specs()
-        table = AT.tune(recs, sample=autotune_sample, reps=2)
+        table = AT.tune(recs, sample=autotune_sample, reps=1)
         AT.apply(recs, table)
         tab.apply_walk(recs)
         tuned = {"seconds": time.perf_counter() - ta, "sample_per_class": autotune_sample, "classes": len(table),
@@ -638,7 +644,7 @@ def main():
     ap.add_argument("--no-c3", dest="c3", action="store_false",
                     help="skip the batched-uneven workload (4,096 jobs of their own populations)")
     ap.add_argument("--c3-steps", type=int, default=2, help="timed steps of the batched-uneven workload")
-    ap.add_argument("--c3-autotune-sample", type=int, default=4,
+    ap.add_argument("--c3-autotune-sample", type=int, default=2,
                     help="jobs timed per (d, log2 n) class by the autotuner on the batched-uneven workload (0: off)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain MIB-MiB device copy (counter calibration) and exit")

@@ -205,8 +205,12 @@ def serve_serial(executor, requests: Sequence[Request], open_loop: bool = True,
 
 
 class GpuExecutor:
-    """Executor over libsnaps: one stream per in-flight batch slot; alerts go
-    up from pinned host buffers and results come back the same way."""
+    """Executor over libsnaps: one stream per in-flight batch slot.  Each
+    slot owns pinned host staging buffers, reused from batch to batch (grown
+    when a batch needs more): a batch's alerts are packed into one of them
+    and go up in one copy, all its outputs come back in one copy into the
+    other, and are copied out into ordinary host arrays once the batch has
+    finished, so no pinned memory stays with a request."""
 
     def __init__(self, states: Dict[Tuple[int, int], object], n_streams: int = 4, device="cuda"):
         import torch
@@ -216,39 +220,65 @@ class GpuExecutor:
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.free = list(range(n_streams))
+        self.h_in = [torch.empty(0, dtype=torch.float32).pin_memory() for _ in range(n_streams)]
+        self.h_out = [torch.empty(0, dtype=torch.int32).pin_memory() for _ in range(n_streams)]
+
+    def _host(self, bufs, si, n, dtype):
+        torch = self.torch
+        if bufs[si].numel() < n:
+            bufs[si] = torch.empty(max(n, 2 * bufs[si].numel()), dtype=dtype).pin_memory()
+        return bufs[si]
 
     def launch(self, batch: List[Request]):
         torch, S = self.torch, self.S
         si = self.free.pop()
         stream = self.streams[si]
-        jobs, hosts = [], []
+        sizes = [r.alerts.size for r in batch]
+        ms = [r.m for r in batch]
+        n_in, n_al = sum(sizes), sum(ms)
+        hin = self._host(self.h_in, si, n_in, torch.float32)
+        hout = self._host(self.h_out, si, 8 * n_al, torch.int32)
+        hv = hin.numpy()
+        at = 0
+        for r, sz in zip(batch, sizes):
+            hv[at:at + sz] = r.alerts.ravel()
+            at += sz
         with torch.cuda.stream(stream):
-            for r in batch:
+            dev_in = hin[:n_in].to(self.device, non_blocking=True)
+            dev_out = torch.empty(8 * n_al, dtype=torch.int32, device=self.device)
+            # per alert of the batch: eps_count, eps_mean, indeg, knn_mean, then the 4 ranks
+            cnt, mean = dev_out[:n_al], dev_out[n_al:2 * n_al].view(torch.float32)
+            deg, kmean = dev_out[2 * n_al:3 * n_al], dev_out[3 * n_al:4 * n_al].view(torch.float32)
+            rank = dev_out[4 * n_al:]
+            jobs, at, ai = [], 0, 0
+            for r, sz, m in zip(batch, sizes, ms):
                 st = self.states[r.key]
-                ha = torch.from_numpy(r.alerts).pin_memory()
-                a = ha.to(self.device, non_blocking=True)
-                j = S.AlertJob.alloc(st, a)
-                jobs.append(j)
-                hosts.append(ha)
+                a = dev_in[at:at + sz].view(m, r.alerts.shape[1])
+                jobs.append(S.AlertJob(st, a, cnt[ai:ai + m], mean[ai:ai + m], deg[ai:ai + m], kmean[ai:ai + m],
+                                       rank[4 * ai:4 * (ai + m)].view(4, m)))
+                at += sz
+                ai += m
             S.snaps_alerts_score(jobs, stream=stream)
-            outs = []
-            for j in jobs:
-                o = {}
-                for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
-                    t = getattr(j, key)
-                    h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
-                    h.copy_(t, non_blocking=True)
-                    o[key] = h
-                outs.append(o)
+            hout[:8 * n_al].copy_(dev_out, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
-        return (si, ev, jobs, hosts, outs)
+        return (si, ev, ms, dev_in, dev_out)
 
     def poll(self, h) -> bool:
         return h[1].query()
 
     def finish(self, h):
-        si, ev, jobs, hosts, outs = h
+        si, ev, ms, _, _ = h
         ev.synchronize()
+        n_al = sum(ms)
+        v = self.h_out[si][:8 * n_al].numpy()
+        out, ai = [], 0
+        for m in ms:
+            out.append({"eps_count": v[ai:ai + m].copy(),
+                        "eps_mean": v[n_al + ai:n_al + ai + m].view(np.float32).copy(),
+                        "indeg": v[2 * n_al + ai:2 * n_al + ai + m].copy(),
+                        "knn_mean": v[3 * n_al + ai:3 * n_al + ai + m].view(np.float32).copy(),
+                        "rank": v[4 * n_al + 4 * ai:4 * n_al + 4 * (ai + m)].reshape(4, m).copy()})
+            ai += m
         self.free.append(si)
-        return [{k: v.numpy() for k, v in o.items()} for o in outs]
+        return out
