@@ -46,9 +46,14 @@
  *   Numerics: distances are evaluated in float32 in the direct form
  *             sum_f (x_f - y_f)^2; eps sums are accumulated in float64.
  *   Limits:   2 <= n <= 2^30 objects per job (larger n returns
- *             SNAPS_EUNSUPPORTED); 1 <= k <= min(32, n - 1).  Jobs with
- *             n <= 32768 are indexed and ranked inside one workgroup's LDS,
- *             larger ones through a device-wide radix sort.
+ *             SNAPS_EUNSUPPORTED); 1 <= k <= n - 1.  Up to k = 32 the kNN
+ *             side runs inside the fused join (per-lane top-k lists); above,
+ *             a selection kernel finds each object's k-th (distance, id) key
+ *             exactly by radix selection over recomputed distances, and
+ *             writes sorted kNN lists for k <= 4096 (lists above that are
+ *             refused with SNAPS_EUNSUPPORTED; the scores take any k).  Jobs
+ *             with n <= 32768 are indexed and ranked inside one workgroup's
+ *             LDS, larger ones through a device-wide radix sort.
  */
 #ifndef SNAPS_H
 #define SNAPS_H
@@ -185,7 +190,9 @@ size_t snaps_outlier_scores_workspace(const snaps_job* jobs, int32_t n_jobs,
  * order.
  *   ids   [n][k] int32 device, output: neighbour ids, row i = object i
  *   dist  [n][k] float device, output: their Euclidean distances (or NULL)
- * Returns SNAPS_EINVAL for k < 1, k > n-1, a bad mask or population. */
+ * Returns SNAPS_EINVAL for k < 1, k > n-1, a bad mask or population, and
+ * SNAPS_EUNSUPPORTED for k > 4096.  Above k = 32 no workspace is used (ws may
+ * be NULL). */
 int snaps_knn_selfjoin(const snaps_population* P, uint32_t mask, int32_t k,
                        int32_t* ids, float* dist,
                        void* ws, size_t ws_bytes, void* stream);

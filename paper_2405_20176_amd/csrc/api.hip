@@ -77,7 +77,13 @@ int check_population(const snaps_population* P, uint32_t mask) {
 
 int check_k(int64_t n, int32_t k) {
     if (k < 1 || k > n - 1) return fail(SNAPS_EINVAL, "k must be in [1, n-1] (k = %d, n = %lld)", k, (long long)n);
-    if (k > kMaxK) return fail(SNAPS_EUNSUPPORTED, "k = %d exceeds this version's limit of %d", k, kMaxK);
+    return SNAPS_OK;
+}
+
+// Sorted kNN lists above kMaxK come from an LDS sort of up to kMaxListK keys.
+int check_list_k(int32_t k) {
+    if (k > kMaxListK)
+        return fail(SNAPS_EUNSUPPORTED, "kNN lists are written for k <= %d (k = %d); the scores take any k", kMaxListK, k);
     return SNAPS_OK;
 }
 
@@ -129,6 +135,7 @@ int device_info(DeviceInfo* out) {
 // What one job needs, decided on the host.
 struct JobPlan {
     int32_t n, d, k, kc, ntiles, nchunks;
+    bool bigk;               // k above the fused join's lists: kNN metrics by the selection kernel
     bool large;              // index through the device-wide radix sort (full 32-bit cell keys)
     bool large_rank;         // ranks through the device-wide radix sort (n above one LDS)
     bool rank;               // rank scratch reserved
@@ -150,7 +157,8 @@ JobPlan plan_job(int64_t n, int d, int k, bool with_rank, int index_sort = kInde
     p.n = (int32_t)n;
     p.d = d;
     p.k = k;
-    p.kc = kc_class(k);
+    p.bigk = k > kMaxK;
+    p.kc = p.bigk ? 0 : kc_class(k);        // the fused join then runs the eps side only
     p.ntiles = (int32_t)((n + kTile - 1) / kTile);
     p.nchunks = (int32_t)((n + kRadixChunk - 1) / kRadixChunk);
     p.large_rank = force_large || n > kLdsSortMax;
@@ -218,11 +226,14 @@ bool shape_hier(int shape, int prune) { return prune && (shape == 2 || shape == 
 
 struct MetaLayout {
     size_t table, order, unit_prefix, tile_prefix, super_prefix, counters;
-    size_t li, iseg, ichunk, lr, rseg, rchunk, rsegchunk;
+    size_t li, iseg, ichunk, lr, rseg, rchunk, rsegchunk, bigk, bigk_prefix;
     size_t bytes;
 };
 
-MetaLayout meta_layout(int n_jobs, int n_large, int n_lrank) {
+// Selection-kernel classes: dimensionality 2..16, with or without lists.
+constexpr int kBigKClasses = (kMaxD + 1) * 2;
+
+MetaLayout meta_layout(int n_jobs, int n_large, int n_lrank, int n_bigk = 0) {
     MetaLayout m{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -243,6 +254,8 @@ MetaLayout meta_layout(int n_jobs, int n_large, int n_lrank) {
     m.rseg = take((size_t)4 * n_lrank * sizeof(SortSeg));
     m.rchunk = take((size_t)(n_lrank + 1) * sizeof(int32_t));
     m.rsegchunk = take((size_t)(4 * n_lrank + 1) * sizeof(int32_t));
+    m.bigk = take((size_t)n_bigk * sizeof(BigKJob));
+    m.bigk_prefix = take((size_t)(n_bigk > 0 ? n_bigk + kBigKClasses : 0) * sizeof(int64_t));
     m.bytes = off;
     return m;
 }
@@ -418,10 +431,16 @@ void count_large(const std::vector<RunJob>& jobs, int* n_large, int* n_lrank) {
     }
 }
 
+int count_bigk(const std::vector<RunJob>& jobs) {
+    int c = 0;
+    for (const auto& j : jobs) c += j.plan.bigk ? 1 : 0;
+    return c;
+}
+
 size_t run_workspace(const std::vector<RunJob>& jobs) {
     int nl = 0, nr = 0;
     count_large(jobs, &nl, &nr);
-    size_t b = meta_layout((int)jobs.size(), nl, nr).bytes;
+    size_t b = meta_layout((int)jobs.size(), nl, nr, count_bigk(jobs)).bytes;
     for (const auto& j : jobs) b += j.plan.bytes;
     return b;
 }
@@ -447,9 +466,10 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
     if (rc != SNAPS_OK) return rc;
     int n_large = 0, n_lrank = 0;
     count_large(jobs, &n_large, &n_lrank);
+    const int n_bigk = count_bigk(jobs);
 
     char* base = static_cast<char*>(ws);
-    const MetaLayout ml = meta_layout(n_jobs, n_large, n_lrank);
+    const MetaLayout ml = meta_layout(n_jobs, n_large, n_lrank, n_bigk);
     Meta meta{};
     meta.table = reinterpret_cast<DevJob*>(base + ml.table);
     meta.order = reinterpret_cast<int32_t*>(base + ml.order);
@@ -493,6 +513,44 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         tile_prefix[i + 1] = (int32_t)total_tiles;
         total_supers += r.plan.nsuper;
         super_prefix[i + 1] = (int32_t)total_supers;
+    }
+
+    // Jobs with k above the fused join's lists: their kNN side runs in the
+    // selection kernel, one launch per (dimensionality, lists) class.
+    std::vector<std::vector<BigKJob>> bk_cls(kBigKClasses);
+    for (int i = 0; i < n_jobs; ++i) {
+        const RunJob& r = jobs[i];
+        if (!r.plan.bigk) continue;
+        BigKJob b{};
+        b.cols = r.pop->cols;
+        b.ld = r.pop->ld;
+        b.n = r.plan.n;
+        b.k = r.plan.k;
+        for (int f = 0; f < kMaxD; ++f) b.feat[f] = table[i].feat[f];
+        b.indeg = r.indeg;
+        b.knn_mean = r.knn_mean;
+        b.ids = r.knn_ids;
+        b.dist = r.knn_dist;
+        bk_cls[r.plan.d * 2 + (r.knn_ids ? 1 : 0)].push_back(b);
+    }
+    std::vector<BigKJob> bk_table;
+    std::vector<int64_t> bk_prefix;
+    std::vector<int> bk_off(kBigKClasses), bk_poff(kBigKClasses);
+    std::vector<int64_t> bk_queries(kBigKClasses, 0);
+    if (n_bigk > 0) {
+        for (int c = 0; c < kBigKClasses; ++c) {
+            bk_off[c] = (int)bk_table.size();
+            bk_poff[c] = (int)bk_prefix.size();
+            int64_t acc = 0;
+            bk_prefix.push_back(0);
+            for (const BigKJob& b : bk_cls[c]) {
+                bk_table.push_back(b);
+                acc += b.n;
+                bk_prefix.push_back(acc);
+            }
+            bk_queries[c] = acc;
+            if (acc > INT32_MAX) return fail(SNAPS_EUNSUPPORTED, "too many queries of large k in one call");
+        }
     }
 
     // Group jobs into kernel classes (dimensionality, top-k capacity); within
@@ -601,7 +659,7 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
     const bool do_index = (tn.passes & SNAPS_PASS_INDEX) != 0;
     const bool do_join = (tn.passes & SNAPS_PASS_JOIN) != 0;
     const bool do_rank = (tn.passes & SNAPS_PASS_RANK) != 0;
-    const bool seed_single = (n_jobs == 1 && n_large == 0);
+    const bool seed_single = (n_jobs == 1 && n_large == 0 && n_bigk == 0);
     if (seed_single) {
         // The metadata of a single small job is written by its index kernel
         // from kernel arguments (no host-to-device copy); later passes of the
@@ -640,6 +698,8 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         put(ml.rseg, rseg.data(), rseg.size() * sizeof(SortSeg));
         put(ml.rchunk, rchunk.data(), rchunk.size() * sizeof(int32_t));
         put(ml.rsegchunk, rsegchunk.data(), rsegchunk.size() * sizeof(int32_t));
+        put(ml.bigk, bk_table.data(), bk_table.size() * sizeof(BigKJob));
+        put(ml.bigk_prefix, bk_prefix.data(), bk_prefix.size() * sizeof(int64_t));
         e = hipMemcpyAsync(base, st.data(), ml.bytes, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "job table upload");
     }
@@ -669,6 +729,15 @@ int run(const std::vector<RunJob>& jobs, const Tune& tn, void* ws, size_t ws_byt
         if (e != hipSuccess) return hip_fail(e, "in-degree reset launch");
         rc = launch_joins(meta, plans, tn, mq, di.cus, s);
         if (rc != SNAPS_OK) return rc;
+        for (int c = 0; c < kBigKClasses; ++c) {
+            if (bk_cls[c].empty()) continue;
+            BigKArgs ba{};
+            ba.table = reinterpret_cast<const BigKJob*>(base + ml.bigk) + bk_off[c];
+            ba.prefix = reinterpret_cast<const int64_t*>(base + ml.bigk_prefix) + bk_poff[c];
+            ba.n_jobs = (int32_t)bk_cls[c].size();
+            e = launch_bigk(c / 2, (c % 2) != 0, ba, bk_queries[c], s);
+            if (e != hipSuccess) return hip_fail(e, "large-k selection launch");
+        }
     }
     bool any_rank = false;
     for (const auto& j : jobs) any_rank |= (j.rank != nullptr);
@@ -714,10 +783,12 @@ size_t snaps_workspace_bytes(int32_t op, int64_t n, int32_t d, int32_t k) {
     if (op == SNAPS_OP_RANK) return rank_workspace(n);
     if (d < 2 || d > kMaxD) return 0;
     if (op == SNAPS_OP_EPS) k = 0;
-    else if (k < 1 || k > n - 1 || k > kMaxK) return 0;
+    else if (k < 1 || k > n - 1) return 0;
     if (op != SNAPS_OP_KNN && op != SNAPS_OP_EPS && op != SNAPS_OP_SCORES) return 0;
+    if (op == SNAPS_OP_KNN && k > kMaxK) return k > kMaxListK ? 0 : kAlign;   // selection kernel: no workspace
     const JobPlan p = plan_job(n, d, k, op == SNAPS_OP_SCORES);
-    const size_t run = meta_layout(1, p.large ? 1 : 0, (p.large_rank && op == SNAPS_OP_SCORES) ? 1 : 0).bytes + p.bytes;
+    const size_t run = meta_layout(1, p.large ? 1 : 0, (p.large_rank && op == SNAPS_OP_SCORES) ? 1 : 0,
+                                   p.bigk ? 1 : 0).bytes + p.bytes;
     return op == SNAPS_OP_EPS ? align_up(run) + pair_scan_scratch(n) : run;
 }
 
@@ -758,6 +829,10 @@ static int collect_jobs(const snaps_job* jobs, int32_t n_jobs, const snaps_tunin
         r.index_dims = j.index_dims;
         r.tile_shape = j.tile_shape;
         if (j.knn_dist && !j.knn_ids) return fail(SNAPS_EINVAL, "job %d: knn_dist needs knn_ids", i);
+        if (j.knn_ids && j.k > kMaxK) {
+            rc = check_list_k(j.k);
+            if (rc != SNAPS_OK) return fail(rc, "job %d: %s", i, g_error.c_str());
+        }
         r.knn_ids = j.knn_ids;
         r.knn_dist = j.knn_dist;
         out->push_back(r);
@@ -779,6 +854,25 @@ int snaps_knn_selfjoin(const snaps_population* P, uint32_t mask, int32_t k, int3
     rc = check_k(P->n, k);
     if (rc != SNAPS_OK) return rc;
     if (!ids) return fail(SNAPS_EINVAL, "ids is NULL");
+    if (k > kMaxK) {
+        // selection kernel, straight from the population's columns
+        rc = check_list_k(k);
+        if (rc != SNAPS_OK) return rc;
+        BigKArgs ba{};
+        ba.use_single = 1;
+        ba.single.cols = P->cols;
+        ba.single.ld = P->ld;
+        ba.single.n = (int32_t)P->n;
+        ba.single.k = k;
+        int f = 0;
+        for (int b = 0; b < 32; ++b)
+            if ((mask >> b) & 1u) ba.single.feat[f++] = b;
+        ba.single.ids = ids;
+        ba.single.dist = dist;
+        hipError_t e = launch_bigk(popcount32(mask), true, ba, P->n, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, "large-k selection launch");
+        return SNAPS_OK;
+    }
     RunJob r{};
     r.pop = P;
     r.mask = mask;

@@ -12,7 +12,8 @@ constexpr int kSuper = 64;           // tiles per super-tile (the join culls the
 constexpr int kMaxD = 16;            // largest subspace dimensionality
 constexpr int kMaxIndexDims = 6;     // c <= 6 indexed dimensions (paper Sec. 3.8.1)
 constexpr int kLdsSortMax = 32768;   // largest n sorted inside one workgroup's LDS
-constexpr int kMaxK = 32;            // largest k
+constexpr int kMaxK = 32;            // largest k of the fused join (larger k: the selection kernel)
+constexpr int kMaxListK = 4096;      // largest k whose sorted lists the selection kernel writes
 constexpr int kSortThreads = 1024;
 constexpr int kRadixChunk = 4096;    // elements per workgroup of the device-wide radix sort
 
@@ -248,6 +249,25 @@ struct KGridJob {
     int32_t* indeg;          // [g][n]
 };
 
+// kNN metrics (and lists) of one job with k above kMaxK, by selection.
+struct BigKJob {
+    const float* cols;       // population columns, cols[f * ld + i]
+    int64_t ld;
+    int32_t n, k;
+    int32_t feat[kMaxD];     // population columns of the subspace, ascending
+    int32_t* indeg;          // [n] added to (atomics), or null
+    float* knn_mean;         // [n] or null
+    int32_t* ids;            // [n][k] or null (k <= kMaxListK)
+    float* dist;             // [n][k] or null
+};
+struct BigKArgs {
+    const BigKJob* table;    // jobs of one (d, lists) class
+    const int64_t* prefix;   // [n_jobs + 1] queries before each job
+    int32_t n_jobs;
+    int32_t use_single;      // 1: the single job below, blocks = its queries
+    BigKJob single;
+};
+
 struct RankArgs {
     const DevJob* table;
     int32_t n_jobs;
@@ -279,6 +299,9 @@ hipError_t launch_eps_sample(const EpsJob* jobs, const int32_t* prefix, int n_jo
 hipError_t launch_ensemble(const DevJob* table, int n_jobs, const int32_t* tile_prefix, int total_tiles,
                            hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t n, int32_t v, hipStream_t s);
+// Selection kernel for k above kMaxK: one workgroup per query of the jobs of
+// one dimensionality D; lists: the jobs write sorted kNN lists.
+hipError_t launch_bigk(int D, bool lists, const BigKArgs& a, int64_t queries, hipStream_t s);
 // Zero the in-degree output of every job of a call (start of the join pass).
 hipError_t launch_zero_indeg(const Meta& m, int32_t n_jobs, int32_t total_tiles, hipStream_t s);
 // off[0] = 0, off[i + 1] = off[i] + count[i] (int64), i < n; scratch holds

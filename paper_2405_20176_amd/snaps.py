@@ -24,7 +24,8 @@ SNAPS_EUNSUPPORTED = -4
 OP_KNN, OP_EPS, OP_SCORES, OP_RANK = 0, 1, 2, 3
 MAX_N = 1 << 30
 LDS_N = 32768          # jobs up to this size are indexed and ranked inside LDS
-MAX_K = 32
+MAX_K = 32             # largest k of the fused join (larger k: the selection kernel)
+MAX_LIST_K = 4096      # largest k whose sorted kNN lists are written
 
 
 class SnapsError(RuntimeError):

@@ -48,6 +48,9 @@ def test_workspace_sizes(lib):
     assert lib.snaps_workspace_bytes(OP_SCORES, 1, 3, 1) == 0          # n < 2
     assert lib.snaps_workspace_bytes(OP_KNN, 100, 3, 100) == 0         # k > n-1
     assert lib.snaps_workspace_bytes(OP_KNN, 100, 17, 5) == 0          # d > 16
+    assert lib.snaps_workspace_bytes(OP_KNN, 100, 3, 40) > 0           # k above the fused join: selection kernel
+    assert lib.snaps_workspace_bytes(OP_KNN, 6000, 3, 5000) == 0       # lists above k = 4096 are not written
+    assert lib.snaps_workspace_bytes(OP_SCORES, 6000, 3, 5000) > 0     # the scores take any k
     assert lib.snaps_workspace_bytes(OP_EPS, 100, 3, 0) > 0
     assert lib.snaps_workspace_bytes(OP_RANK, 100, 0, 0) == 0          # LDS-resident rank needs none
     assert lib.snaps_workspace_bytes(OP_RANK, 40000, 0, 0) > 8 * 40000 * 4
@@ -66,7 +69,6 @@ def _pop(n=100, f=15):
     (1 << 15, 5, -1),        # beyond n_features
     (0b111, 0, -1),          # k < 1
     (0b111, 100, -1),        # k > n - 1
-    (0b111, 40, -4),         # k beyond the supported 32
 ])
 def test_knn_validation(lib, mask, k, expect):
     p = _pop()
@@ -74,6 +76,23 @@ def test_knn_validation(lib, mask, k, expect):
     rc = lib.snaps_knn_selfjoin(ctypes.byref(p), mask, k, ids, None, None, 0, None)
     assert rc == expect, lib.snaps_last_error()
     assert lib.snaps_last_error()
+
+
+def test_large_k_list_limit(lib):
+    """Sorted kNN lists are written up to k = 4096; above, the call is
+    refused before any device work (the scores alone take any k <= n - 1)."""
+    from paper_2405_20176_amd.snaps import c_job, c_population, c_scores
+    p = c_population(0x1000, 6016, 6000, 15)
+    ids = ctypes.c_void_p(0x2000)
+    assert lib.snaps_knn_selfjoin(ctypes.byref(p), 0b111, 4097, ids, None, None, 0, None) == -4
+    assert lib.snaps_knn_selfjoin(ctypes.byref(p), 0b111, 6000, ids, None, None, 0, None) == -1   # k > n - 1
+    job = c_job()
+    job.pop = ctypes.pointer(p)
+    job.mask, job.k, job.eps = 0b111, 5000, 0.1
+    job.out = c_scores(0x10, 0x20, 0x30, 0x40)
+    assert lib.snaps_outlier_scores_workspace(ctypes.byref(job), 1, None) > 0
+    job.knn_ids = 0x50
+    assert lib.snaps_outlier_scores(ctypes.byref(job), 1, None, None, 0, None) == -4
 
 
 def test_eps_validation(lib):
