@@ -409,11 +409,11 @@ int snaps_eps_grid(const snaps_eps_grid_job* jobs, int32_t n_jobs, void* ws, siz
  * (U^min) and k_g (U^max), and the index of the k minimising |U^min - U^max|
  * (the first of equal gaps).  Metric 0 is the in-degree (ascending), metric 1
  * the mean kNN distance (descending) (Sec. 3.6.1). */
-#define SNAPS_MAX_KGRID_N 32768      /* largest population of a k-grid job */
 #define SNAPS_MAX_KGRID_K 4096       /* largest k of a k grid */
 typedef struct {
     const snaps_population* pop;   /* columns 16-byte aligned and ld a multiple of 4, as for the eps grid;
-                                      n in [2, SNAPS_MAX_KGRID_N] */
+                                      n >= 2 (each query's distances are held in registers up to
+                                      32,768 objects and recomputed in every selection pass above) */
     uint32_t mask;                 /* subspace */
     int32_t n_grid;                /* 2..SNAPS_MAX_GRID */
     int32_t k[SNAPS_MAX_GRID];     /* strictly ascending, k_1 >= 1, k_g <= min(SNAPS_MAX_KGRID_K, n - 1) */

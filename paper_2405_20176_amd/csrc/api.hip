@@ -1600,8 +1600,9 @@ int plan_kgrid(const snaps_k_grid_job* jobs, int32_t n_jobs, KGridPlan* p) {
         const int64_t n = j.pop->n;
         if ((reinterpret_cast<uintptr_t>(j.pop->cols) & 15u) != 0 || (j.pop->ld & 3) != 0)
             return fail(SNAPS_EINVAL, "k-grid job %d: columns must be 16-byte aligned with ld a multiple of 4", i);
-        if (n < 2 || n > kMaxKGridN)
-            return fail(SNAPS_EUNSUPPORTED, "k-grid job %d: n = %lld outside [2, %d]", i, (long long)n, kMaxKGridN);
+        if (n < 2 || n > kMaxN)
+            return fail(SNAPS_EUNSUPPORTED, "k-grid job %d: n = %lld outside [2, %lld]", i, (long long)n,
+                        (long long)kMaxN);
         if (j.n_grid < 2 || j.n_grid > kMaxGrid)
             return fail(SNAPS_EINVAL, "k-grid job %d: n_grid must be in [2, %d]", i, kMaxGrid);
         for (int g = 0; g < j.n_grid; ++g) {
@@ -1651,14 +1652,18 @@ int snaps_k_grid(const snaps_k_grid_job* jobs, int32_t n_jobs, void* ws, size_t 
     table.reserve(n_jobs);
     gtable.reserve(n_jobs);
     std::vector<int32_t> qprefix, tprefix;
-    struct Group { int d, first, count, queries, tiles, prefix_at; };
+    // Launch groups: one dimensionality, and populations within one
+    // workgroup's registers or above (the streaming threshold kernel).
+    struct Group { int d, stream, first, count, queries, tiles, prefix_at; };
     std::vector<Group> groups;
-    for (int d = 2; d <= kMaxD; ++d) {
-        Group g{d, (int)table.size(), 0, 0, 0, (int)qprefix.size()};
+    for (int gi = 0; gi < 2 * (kMaxD + 1); ++gi) {
+        const int d = gi / 2, stream = gi % 2;
+        if (d < 2) continue;
+        Group g{d, stream, (int)table.size(), 0, 0, 0, (int)qprefix.size()};
         qprefix.push_back(0);
         tprefix.push_back(0);
         for (int i = 0; i < n_jobs; ++i) {
-            if (p.d[i] != d) continue;
+            if (p.d[i] != d || (jobs[i].pop->n > kMaxKGridN ? 1 : 0) != stream) continue;
             const snaps_k_grid_job& j = jobs[i];
             const int32_t n = (int32_t)j.pop->n;
             KGridJob e{};
@@ -1691,6 +1696,7 @@ int snaps_k_grid(const snaps_k_grid_job* jobs, int32_t n_jobs, void* ws, size_t 
             s2.select = j.select;
             gtable.push_back(s2);
             g.count += 1;
+            if ((int64_t)g.queries + n > INT32_MAX) return fail(SNAPS_EUNSUPPORTED, "too many k-grid queries in one call");
             g.queries += n;
             const int tg = kgrid_tiles_per_group();
             g.tiles += ((n + kTile - 1) / kTile + tg - 1) / tg;      // groups of tiles
@@ -1721,7 +1727,8 @@ int snaps_k_grid(const snaps_k_grid_job* jobs, int32_t n_jobs, void* ws, size_t 
     const int32_t* dq = reinterpret_cast<const int32_t*>(base + p.prefix);
     const int32_t* dtp = dq + qprefix.size();
     for (const Group& g : groups) {
-        e = launch_kgrid(dt + g.first, dq + g.prefix_at, dtp + g.prefix_at, g.count, g.queries, g.tiles, g.d, s);
+        e = launch_kgrid(dt + g.first, dq + g.prefix_at, dtp + g.prefix_at, g.count, g.queries, g.tiles, g.d,
+                         g.stream != 0, s);
         if (e != hipSuccess) return hip_fail(e, "k-grid launch");
     }
     e = launch_grid_select(dg, n_jobs, s);

@@ -3,9 +3,11 @@
 // in-degree and the mean kNN distance of every object at every k, from the
 // k_max nearest neighbours, which hold those of every smaller k.
 //   k_kgrid_thresh: one workgroup per query, its distances to every object
-//     held in registers.  One radix selection for all k_j at once gives, for
-//     every k_j, the (distance, id) bound of the k_j nearest (ties in id
-//     order) and the sum of the k_j smallest distances.
+//     held in registers (k_kgrid_thresh_stream, for populations above
+//     kMaxKGridN objects: recomputed in every pass).  One radix selection
+//     for all k_j at once gives, for every k_j, the (distance, id) bound of
+//     the k_j nearest (ties in id order) and the sum of the k_j smallest
+//     distances.
 //   k_kgrid_indeg: one lane per object p scans every query q: p is among the
 //     k_j nearest of q exactly when (distance, id of p) is at most q's k_j-th
 //     (distance, id), so p's in-degree at every k needs no global atomics.
@@ -326,6 +328,233 @@ __global__ __launch_bounds__(kThreshThreads) void k_kgrid_thresh(const KGridJob*
     }
 }
 
+// The same selection for populations above one workgroup's registers
+// (n > kMaxKGridN): every pass recomputes the query's distances from the
+// columns instead of holding them (the same operations, so the same float32
+// values), and ties are split by id over 32 bits.
+template <typename GetFn>
+__device__ __forceinline__ unsigned select_digit_stream(GetFn get, int n, int shift, int bits, unsigned pre,
+                                                        unsigned& r, unsigned* hist, int* tmp, unsigned* s_sel) {
+    const int tid = threadIdx.x;
+    const int nb = 1 << bits;
+    for (int x = tid; x < nb; x += kThreshThreads) hist[x] = 0u;
+    __syncthreads();
+    for (int i = tid; i < n; i += kThreshThreads) {
+        bool on;
+        const uint32_t v = get(i, on);
+        if (on && (shift + bits >= 32 || (v >> (shift + bits)) == pre))
+            atomicAdd(&hist[(v >> shift) & (unsigned)(nb - 1)], 1u);
+    }
+    __syncthreads();
+    const int per = (nb + kThreshThreads - 1) / kThreshThreads;
+    const int b0 = tid * per;
+    unsigned local = 0u;
+    for (int b = 0; b < per; ++b)
+        if (b0 + b < nb) local += hist[b0 + b];
+    int total;
+    const unsigned before = (unsigned)block_exclusive_scan((int)local, tmp, &total);
+    if (before < r && before + local >= r) {
+        unsigned cum = before;
+        int b = b0;
+        while (cum + hist[b] < r) cum += hist[b++];
+        s_sel[0] = (pre << bits) | (unsigned)b;
+        s_sel[1] = r - cum;
+    }
+    __syncthreads();
+    const unsigned out = s_sel[0];
+    r = s_sel[1];
+    __syncthreads();
+    return out;
+}
+
+template <int D>
+__global__ __launch_bounds__(kThreshThreads) void k_kgrid_thresh_stream(const KGridJob* jobs, const int32_t* prefix,
+                                                                         int n_jobs, int block0) {
+    __shared__ unsigned hist[kMaxGrid * 1024];
+    __shared__ uint8_t tab1[4096];
+    __shared__ uint8_t tab2[kMaxGrid][1024];
+    __shared__ uint32_t list[kMaxKGridK];
+    __shared__ unsigned s_pre[kMaxGrid], s_rank[kMaxGrid], s_id[kMaxGrid];
+    __shared__ unsigned s_g1[kMaxGrid], s_g2[kMaxGrid];
+    __shared__ double s_part[kThreshThreads / 64][kMaxGrid];
+    __shared__ int tmp[17];
+    __shared__ unsigned s_sel[3];
+    __shared__ unsigned s_fill, s_split;
+    const int blk = block0 + (int)blockIdx.x;
+    const int jb = kjob_of(prefix, n_jobs, blk);
+    const KGridJob& J = jobs[jb];
+    const int qid = blk - prefix[jb];
+    const int n = J.n;
+    const int g = J.g;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    {
+        uint32_t* t1 = reinterpret_cast<uint32_t*>(tab1);
+        uint32_t* t2 = reinterpret_cast<uint32_t*>(&tab2[0][0]);
+        for (int x = tid; x < 4096 / 4; x += kThreshThreads) t1[x] = 0u;
+        for (int x = tid; x < kMaxGrid * 1024 / 4; x += kThreshThreads) t2[x] = 0u;
+        for (int x = tid; x < 4096; x += kThreshThreads) hist[x] = 0u;
+        if (tid == 0) {
+            s_fill = 0u;
+            s_split = 0u;
+        }
+    }
+    const float* col[D];
+    float q[D];
+#pragma unroll
+    for (int f = 0; f < D; ++f) {
+        col[f] = J.cols + (int64_t)J.feat[f] * J.ld;
+        q[f] = col[f][qid];
+    }
+    auto dist_bits = [&](int i) -> uint32_t {
+        float dd = 0.f;
+#pragma unroll
+        for (int f = 0; f < D; ++f) {
+            const float tq = q[f] - col[f][i];                                  // query minus object
+            dd = fmaf(tq, tq, dd);
+        }
+        return i == qid ? 0x7F800000u : __float_as_uint(dd);                    // self: +inf, never chosen
+    };
+    __syncthreads();
+
+    // Pass 0: bits [31:20], one histogram for every target.
+    for (int i = tid; i < n; i += kThreshThreads) atomicAdd(&hist[dist_bits(i) >> 20], 1u);
+    __syncthreads();
+    const unsigned R = (unsigned)J.k[wave];
+    {
+        unsigned b, below, size;
+        wave_rank_bin(hist, 4096 / 64, R, &b, &below, &size);
+        if (lane == 0) {
+            s_pre[wave] = b;
+            s_rank[wave] = R - below;
+        }
+    }
+    __syncthreads();
+    // Pass 1: bits [19:10], a histogram per distinct 12-bit prefix.
+    if (tid < kMaxGrid) {
+        unsigned grp = 0u;
+        for (int t = 1; t <= tid; ++t) grp += s_pre[t] != s_pre[t - 1] ? 1u : 0u;
+        s_g1[tid] = grp;
+        tab1[s_pre[tid]] = (uint8_t)(grp + 1u);
+    }
+    for (int x = tid; x < kMaxGrid * 1024; x += kThreshThreads) hist[x] = 0u;
+    __syncthreads();
+    for (int i = tid; i < n; i += kThreshThreads) {
+        const uint32_t v = dist_bits(i);
+        const unsigned g1 = tab1[v >> 20];
+        if (g1) atomicAdd(&hist[(g1 - 1u) * 1024u + ((v >> 10) & 1023u)], 1u);
+    }
+    __syncthreads();
+    {
+        unsigned b, below, size;
+        wave_rank_bin(hist + s_g1[wave] * 1024u, 1024 / 64, s_rank[wave], &b, &below, &size);
+        if (lane == 0) {
+            s_pre[wave] = (s_pre[wave] << 10) | b;
+            s_rank[wave] -= below;
+        }
+    }
+    __syncthreads();
+    // Pass 2: bits [9:0], a histogram per distinct 22-bit prefix.
+    if (tid < kMaxGrid) {
+        unsigned grp = 0u;
+        for (int t = 1; t <= tid; ++t) grp += s_pre[t] != s_pre[t - 1] ? 1u : 0u;
+        s_g2[tid] = grp;
+        tab2[s_g1[tid]][s_pre[tid] & 1023u] = (uint8_t)(grp + 1u);
+    }
+    for (int x = tid; x < kMaxGrid * 1024; x += kThreshThreads) hist[x] = 0u;
+    __syncthreads();
+    for (int i = tid; i < n; i += kThreshThreads) {
+        const uint32_t v = dist_bits(i);
+        const unsigned g1 = tab1[v >> 20];
+        if (!g1) continue;
+        const unsigned g2 = tab2[g1 - 1u][(v >> 10) & 1023u];
+        if (g2) atomicAdd(&hist[(g2 - 1u) * 1024u + (v & 1023u)], 1u);
+    }
+    __syncthreads();
+    {
+        unsigned b, below, size;
+        wave_rank_bin(hist + s_g2[wave] * 1024u, 1024 / 64, s_rank[wave], &b, &below, &size);
+        if (lane == 0) {
+            s_pre[wave] = (s_pre[wave] << 10) | b;
+            s_rank[wave] -= below;
+            s_id[wave] = 0xFFFFFFFFu;               // every tie at the distance belongs
+            if (size > s_rank[wave]) atomicOr(&s_split, 1u << wave);
+        }
+    }
+    __syncthreads();
+    // Ties split by id: the s_rank-th smallest id among the ties, 4 x 8 bits.
+    for (unsigned todo = s_split; todo; todo &= todo - 1u) {
+        const int t = __builtin_ctz(todo);
+        const unsigned vt = s_pre[t], rt = s_rank[t];
+        if (t > 0 && vt == s_pre[t - 1] && rt == s_rank[t - 1]) {
+            if (tid == 0) s_id[t] = s_id[t - 1];
+            __syncthreads();
+            continue;
+        }
+        auto id_of_tie = [&](int i, bool& on) {
+            on = dist_bits(i) == vt;
+            return (uint32_t)i;
+        };
+        unsigned r = rt;
+        unsigned id = select_digit_stream(id_of_tie, n, 24, 8, 0u, r, hist, tmp, s_sel);
+        id = select_digit_stream(id_of_tie, n, 16, 8, id, r, hist, tmp, s_sel);
+        id = select_digit_stream(id_of_tie, n, 8, 8, id, r, hist, tmp, s_sel);
+        id = select_digit_stream(id_of_tie, n, 0, 8, id, r, hist, tmp, s_sel);
+        if (tid == 0) s_id[t] = id;
+        __syncthreads();
+    }
+
+    // Sums of the distances below each target's (as in k_kgrid_thresh).
+    const uint32_t vtop = s_pre[kMaxGrid - 1];
+    for (int i0 = 0; i0 < n; i0 += kThreshThreads) {
+        const int i = i0 + tid;
+        const uint32_t v = i < n ? dist_bits(i) : 0xFFFFFFFFu;
+        const bool in = v < vtop;
+        const unsigned long long bal = __ballot(in);
+        unsigned base = 0u;
+        if (lane == 0 && bal) base = atomicAdd(&s_fill, (unsigned)__popcll(bal));
+        base = __shfl(base, 0, 64);
+        const unsigned pos = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (in && pos < (unsigned)kMaxKGridK) list[pos] = v;
+    }
+    __syncthreads();
+    const int m = (int)min(s_fill, (unsigned)kMaxKGridK);
+    uint32_t vt[kMaxGrid];
+#pragma unroll
+    for (int t = 0; t < kMaxGrid; ++t) vt[t] = s_pre[t];
+    double part[kMaxGrid];
+#pragma unroll
+    for (int t = 0; t < kMaxGrid; ++t) part[t] = 0.0;
+    for (int x = tid; x < m; x += kThreshThreads) {
+        const uint32_t v = list[x];
+        int c = 0;
+#pragma unroll
+        for (int t = 0; t < kMaxGrid; ++t) c += v >= vt[t] ? 1 : 0;
+        const double dv = (double)sqrtf(__uint_as_float(v));
+#pragma unroll
+        for (int t = 0; t < kMaxGrid; ++t) part[t] += c == t ? dv : 0.0;
+    }
+    {
+        double run = 0.0;
+#pragma unroll
+        for (int t = 0; t < kMaxGrid; ++t) {
+            run += wave_scan_dpp(part[t]);
+            if (lane == 63) s_part[wave][t] = run;
+        }
+    }
+    __syncthreads();
+    if (tid < kMaxGrid) {
+        const int t = tid;
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < kThreshThreads / 64; ++w) sum += s_part[w][t];
+        sum += (double)s_rank[t] * (double)sqrtf(__uint_as_float(vt[t]));
+        J.thr[(int64_t)qid * kMaxGrid + t] = ((uint64_t)vt[t] << 32) | (uint64_t)s_id[t];
+        if (t < g) J.kmean[(int64_t)t * n + qid] = (float)(sum / (double)J.k[t]);
+    }
+}
+
 // Four 64-object tiles of one job per workgroup, lane = object p.  The
 // queries come in chunks of 256, their coordinates and thresholds staged in
 // LDS by the whole workgroup; p is among the k_j nearest of query q exactly
@@ -388,28 +617,28 @@ using KThreshFn = void (*)(const KGridJob*, const int32_t*, int, int);
 using KIndegFn = void (*)(const KGridJob*, const int32_t*, int);
 
 template <int D>
-void kgrid_fns(KThreshFn* a, KIndegFn* b) {
-    *a = k_kgrid_thresh<D>;
+void kgrid_fns(KThreshFn* a, KIndegFn* b, bool stream) {
+    *a = stream ? k_kgrid_thresh_stream<D> : k_kgrid_thresh<D>;
     *b = k_kgrid_indeg<D>;
 }
 
-bool kgrid_pick(int d, KThreshFn* a, KIndegFn* b) {
+bool kgrid_pick(int d, KThreshFn* a, KIndegFn* b, bool stream) {
     switch (d) {
-        case 2: kgrid_fns<2>(a, b); return true;
-        case 3: kgrid_fns<3>(a, b); return true;
-        case 4: kgrid_fns<4>(a, b); return true;
-        case 5: kgrid_fns<5>(a, b); return true;
-        case 6: kgrid_fns<6>(a, b); return true;
-        case 7: kgrid_fns<7>(a, b); return true;
-        case 8: kgrid_fns<8>(a, b); return true;
-        case 9: kgrid_fns<9>(a, b); return true;
-        case 10: kgrid_fns<10>(a, b); return true;
-        case 11: kgrid_fns<11>(a, b); return true;
-        case 12: kgrid_fns<12>(a, b); return true;
-        case 13: kgrid_fns<13>(a, b); return true;
-        case 14: kgrid_fns<14>(a, b); return true;
-        case 15: kgrid_fns<15>(a, b); return true;
-        case 16: kgrid_fns<16>(a, b); return true;
+        case 2: kgrid_fns<2>(a, b, stream); return true;
+        case 3: kgrid_fns<3>(a, b, stream); return true;
+        case 4: kgrid_fns<4>(a, b, stream); return true;
+        case 5: kgrid_fns<5>(a, b, stream); return true;
+        case 6: kgrid_fns<6>(a, b, stream); return true;
+        case 7: kgrid_fns<7>(a, b, stream); return true;
+        case 8: kgrid_fns<8>(a, b, stream); return true;
+        case 9: kgrid_fns<9>(a, b, stream); return true;
+        case 10: kgrid_fns<10>(a, b, stream); return true;
+        case 11: kgrid_fns<11>(a, b, stream); return true;
+        case 12: kgrid_fns<12>(a, b, stream); return true;
+        case 13: kgrid_fns<13>(a, b, stream); return true;
+        case 14: kgrid_fns<14>(a, b, stream); return true;
+        case 15: kgrid_fns<15>(a, b, stream); return true;
+        case 16: kgrid_fns<16>(a, b, stream); return true;
     }
     return false;
 }
@@ -419,10 +648,10 @@ bool kgrid_pick(int d, KThreshFn* a, KIndegFn* b) {
 int kgrid_tiles_per_group() { return kIndegWaves; }
 
 hipError_t launch_kgrid(const KGridJob* jobs, const int32_t* query_prefix, const int32_t* group_prefix, int n_jobs,
-                        int total_queries, int total_groups, int d, hipStream_t s) {
+                        int total_queries, int total_groups, int d, bool stream, hipStream_t s) {
     KThreshFn thresh;
     KIndegFn indeg;
-    if (!kgrid_pick(d, &thresh, &indeg)) return hipErrorInvalidValue;
+    if (!kgrid_pick(d, &thresh, &indeg, stream)) return hipErrorInvalidValue;
     if (n_jobs <= 0) return hipSuccess;
     // A dispatch counts its work-items in 32 bits: launches of at most 2^21
     // workgroups of 1024.

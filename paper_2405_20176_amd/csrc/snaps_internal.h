@@ -234,7 +234,7 @@ struct GridJob {
 };
 
 // k selection on a grid of k (one job = one subspace and grid).
-constexpr int kMaxKGridN = 32768;     // distances of one query held in LDS
+constexpr int kMaxKGridN = 32768;     // distances of one query held in registers (larger: recomputed per pass)
 constexpr int kMaxKGridK = 4096;
 struct KGridJob {
     const float* cols;       // 16-byte aligned columns, ld a multiple of 4
@@ -291,7 +291,7 @@ hipError_t launch_grid_select(const GridJob* jobs, int n_jobs, hipStream_t s);
 // kgrid_tiles_per_group() 64-object tiles.
 int kgrid_tiles_per_group();
 hipError_t launch_kgrid(const KGridJob* jobs, const int32_t* query_prefix, const int32_t* group_prefix, int n_jobs,
-                        int total_queries, int total_groups, int d, hipStream_t s);
+                        int total_queries, int total_groups, int d, bool stream, hipStream_t s);
 hipError_t launch_eps_sample(const EpsJob* jobs, const int32_t* prefix, int n_jobs, int total_blocks, int d,
                              hipStream_t s);
 // Mean of the four ranks of every object of every job with an ensemble

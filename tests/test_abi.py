@@ -252,8 +252,8 @@ def test_k_grid_validation(lib):
         for r, v in enumerate(ks):
             bad.k[r] = v
         assert lib.snaps_k_grid_workspace(ctypes.byref(bad), 1) == 0, ks
-    for cols, ld, n in ((0x1004, 128, 100), (0x1000, 102, 100), (0x1000, 32772, 32769)):
-        q = c_population(cols, ld, n, 15)           # misaligned, ld not a multiple of 4, n beyond LDS
+    for cols, ld, n in ((0x1004, 128, 100), (0x1000, 102, 100)):
+        q = c_population(cols, ld, n, 15)           # misaligned, ld not a multiple of 4
         bad = c_k_grid_job.from_buffer_copy(j)
         bad.pop = ctypes.pointer(q)
         assert lib.snaps_k_grid_workspace(ctypes.byref(bad), 1) == 0, (cols, ld, n)
@@ -264,6 +264,10 @@ def test_k_grid_validation(lib):
     assert lib.snaps_k_grid_workspace(ctypes.byref(big), 1) > 0
     big.k[2] = 4097
     assert lib.snaps_k_grid_workspace(ctypes.byref(big), 1) == 0
+    q2 = c_population(0x1000, 5_000_000, 5_000_000, 15)   # above one workgroup's registers: streaming selection
+    lsst = c_k_grid_job.from_buffer_copy(j)
+    lsst.pop = ctypes.pointer(q2)
+    assert lib.snaps_k_grid_workspace(ctypes.byref(lsst), 1) > 5_000_000 * 16 * 8
 
 
 def test_static_scratch_entry_validation(lib):

@@ -17,7 +17,7 @@ import oracle as O
 from oracle import c_oracle as C
 import snaps_synth as G
 from tests.golden import exact_fp32_variant, load_tab2
-from tests.parity import TAU, check_knn, check_scores, self_ranks
+from tests.parity import TAU, check_knn, check_scores, knn_strict, self_ranks
 
 pytestmark = pytest.mark.gpu
 
@@ -968,3 +968,61 @@ def test_super_tile_walk_and_candidate_halves_large_n(S, d):
     assert ((g["eps_count"][qs] == ora["eps_count"]) | exempt).all()
     check_knn(g["knn_ids"][qs], g["knn_dist"][qs], ora, k, label=f"super-tile walk d={d}", row_ids=qs)
     assert int(g["indeg"].astype(np.int64).sum()) == n * k
+
+
+# --------------------------------------- k grid above one workgroup's registers
+
+@pytest.mark.parametrize("case", ["random", "coarse_grid_ties"])
+def test_k_grid_streaming_selection_above_32768(S, case):
+    """Populations above 32,768 objects take the k-grid threshold kernel that
+    recomputes each query's distances in every selection pass.  At every
+    k <= 64 the in-degree of every object equals the one counted from the
+    oracle's kNN lists (C twin, all 40,000 queries) exactly, except where an
+    exempt query could list it; on a coarse grid (squared distances exact in
+    float32, many ties and duplicates split by id on both sides) exactly
+    everywhere.  Mean kNN distances hold to tau at every k for sampled
+    queries, and the in-degrees sum to n k."""
+    rng = np.random.default_rng(4096)
+    n, d = 40_000, 3
+    if case == "random":
+        x = rng.random((n, d)).astype(np.float32)
+    else:
+        x = (rng.integers(0, 20, size=(n, d)) / 16.0).astype(np.float32)
+    ks = [2, 5, 16, 64, 256]
+    out = S.snaps_k_grid([(S.Population.from_rows(x), (1 << d) - 1, ks, 400)], with_metrics=True)[0]
+    deg = out["indeg"].cpu().numpy().astype(np.int64)
+    km = out["knn_mean"].cpu().numpy().astype(np.float64)
+    for j, k in enumerate(ks):
+        assert deg[j].sum() == n * k, k
+    ora = C.join(x, 64, -1.0)
+    for j, k in enumerate(ks):
+        if k > 64:
+            continue
+        want = O.indegree(ora["knn_ids"][:, :k], n)
+        if case == "random":
+            dk = ora["knn_dist"][:, k - 1]
+            dn = ora["knn_dist"][:, k] if k < 64 else ora["knn_next"]
+            ex = ~knn_strict(dk, dn)
+            # an exempt query lists every object closer than its k-th
+            # distance (1 - tau) on both sides; they differ only in objects
+            # within tau of that distance
+            touched = np.zeros(n, dtype=bool)
+            exq = np.nonzero(ex)[0]
+            if exq.size:
+                Dq = O.pair_distances(x[exq], x)
+                Dq[np.arange(exq.size), exq] = np.inf
+                band = (Dq >= dk[exq, None] * (1 - TAU)) & (Dq <= dk[exq, None] * (1 + TAU))
+                touched[np.nonzero(band)[1]] = True
+            assert ((deg[j] == want) | touched).all(), k
+            assert touched.sum() < n // 100, (k, int(touched.sum()))
+        else:
+            np.testing.assert_array_equal(deg[j], want, err_msg=f"k={k}")
+    qs = np.sort(rng.choice(n, size=48, replace=False))
+    D = O.pair_distances(x[qs], x)
+    D[np.arange(qs.size), qs] = np.inf
+    Ds = np.sort(D, axis=1)
+    for j, k in enumerate(ks):
+        want = Ds[:, :k].mean(axis=1)
+        got = km[j][qs]
+        ok = (np.abs(got - want) <= TAU * want) | ((want == 0) & (got == 0))
+        assert ok.all(), (k, got[~ok][:3], want[~ok][:3])
