@@ -319,7 +319,7 @@ def c3_bench(S, G, lib, dev, stream, steps: int, warmup: int, autotune_sample: i
     return res
 
 
-def c2_bench(S, G, dev, stream, steps: int):
+def c2_bench(S, G, dev, stream, steps: int, lsst_k_grid: bool = False):
     """LSST-scale population: N = 5,000,000 objects (the SNAPShot1-shaped
     generator), the full 15-feature space plus all 105 two-feature spaces,
     k = 10, eps from the stored table (target mean count 20), in one job
@@ -399,6 +399,22 @@ def c2_bench(S, G, dev, stream, steps: int):
     sums = torch.stack([tab.indeg[tab.off[i]:tab.off[i + 1]].sum(dtype=torch.int64) for i in range(len(masks))])
     res["indeg_sums_equal_nk"] = bool((sums.cpu().numpy() == n * k).all())
     del off
+    # the paper's k selection at this scale (k up to 256 as in the LSST
+    # runs, Sec. 4.5): one two-feature space, on request (brute force over
+    # n^2 pairs: minutes)
+    tk = time.perf_counter()
+    if not lsst_k_grid:
+        tk = None
+    if tk is not None:
+        ks = [2, 4, 8, 16, 32, 64, 128, 256]
+        kg = S.snaps_k_grid([(pop, int(masks[1]), ks, max(1, int(round(0.01 * n))))], with_metrics=False)[0]
+        torch.cuda.synchronize()
+        res["k_grid_selection_one_space"] = {
+            "seconds": time.perf_counter() - tk, "mask": int(masks[1]), "grid": ks, "objects": n,
+            "selected_k": [int(ks[i]) for i in kg["select"].cpu().numpy()],
+            "clock": "host wall clock around one k-grid call (thresholds by the streaming selection, "
+                     "in-degrees by comparing every object with every query's bounds)"}
+        log(f"C2: k-grid selection of one two-feature space in {res['k_grid_selection_one_space']['seconds']:.1f} s")
     log(f"C2: {sec:.2f} s per step, {res['value']:.3e} scores/s, join {join_ms:.0f} ms "
         f"(d15 {parts['d15']['join_ms']:.0f} ms frac {parts['d15']['frac']:.2f}, "
         f"105 x d2 {parts['d2_x105']['join_ms']:.0f} ms, {parts['d2_x105']['candidates_per_result']:.1f} cand/result)")
@@ -641,6 +657,8 @@ def main():
     ap.add_argument("--no-c2", dest="c2", action="store_false",
                     help="skip the LSST-scale population (5,000,000 objects, the full space + 105 two-feature spaces)")
     ap.add_argument("--c2-steps", type=int, default=1, help="timed steps of the LSST-scale population")
+    ap.add_argument("--lsst-k-grid", action="store_true",
+                    help="also time the k-grid selection (k = 2..256) of one two-feature space at 5,000,000 objects")
     ap.add_argument("--no-c3", dest="c3", action="store_false",
                     help="skip the batched-uneven workload (4,096 jobs of their own populations)")
     ap.add_argument("--c3-steps", type=int, default=2, help="timed steps of the batched-uneven workload")
@@ -871,7 +889,7 @@ def main():
     if a.c3:
         result["c3"] = c3_bench(S, G, lib, dev, stream, a.c3_steps, 1, a.c3_autotune_sample, not a.no_plain)
     if a.c2:
-        result["c2"] = c2_bench(S, G, dev, stream, a.c2_steps)
+        result["c2"] = c2_bench(S, G, dev, stream, a.c2_steps, a.lsst_k_grid)
     if a.serve_seconds > 0:
         result["serving"] = serve_bench(S, G, dev, a.serve_seconds)
 
