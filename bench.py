@@ -39,8 +39,8 @@ PEAK_FP32_MFMA = 157.3e12        # MI355X published dense FP32 matrix peak, flop
 PEAK_HBM = 8.0e12                # MI355X HBM3E, byte/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_join_c1_all_subspaces_hbm_traffic.md")
 JOIN_SOURCES = ["join_kernel.cuh", "join_mfma.cuh", "join.hip", "join_inst0.hip", "join_inst1.hip",
-                "join_inst2.hip", "join_inst3.hip", "join_mfma0.hip", "join_mfma1.hip", "common.cuh",
-                "snaps_internal.h"]
+                "join_inst2.hip", "join_inst3.hip", "join_mfma0.hip", "join_mfma1.hip", "join_mfma2.hip",
+                "join_mfma3.hip", "common.cuh", "snaps_internal.h"]
 
 
 def log(*a):

@@ -8,9 +8,12 @@
 //   eps_count, indeg   ascending integers, the value itself;
 //   eps_mean           descending, objects without any eps neighbour first;
 //   knn_mean           descending.
-// The keys are sorted in LDS, compacted to their distinct values, and every
-// object's rank is the position of its key among the distinct values
-// (binary search).
+// The float metrics' keys are sorted in LDS, compacted to their distinct
+// values, and every object's rank is the position of its key among the
+// distinct values (binary search).  The integer metrics (values below
+// 32,768 here) need no sort: a bitmap in LDS marks the values present, and
+// an object's rank is the number of marked values below its own (a scan of
+// the words' popcounts, then one popcount within the word).
 #include "snaps_internal.h"
 #include "common.cuh"
 #include "keys.cuh"
@@ -32,6 +35,50 @@ __global__ __launch_bounds__(kSortThreads) void k_rank(RankLaunch L) {
     const int n = J.n;
     const int tid = threadIdx.x;
     const int P = next_pow2(n < 2 ? 2 : n);
+
+    bool small_ints = false;
+    if (metric == 0 || metric == 2) {
+        // integer metric: the bitmap path when every value is below
+        // kLdsSortMax (always for the join's counts and in-degrees here, as
+        // n <= kLdsSortMax; values from a caller of snaps_rank may not be)
+        uint32_t mx = 0u;
+        for (int i = tid; i < n; i += blockDim.x) mx = max(mx, metric_key(J, metric, i));
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+        if ((tid & 63) == 0) tmp[tid >> 6] = (int)mx;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t m = 0u;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = max(m, (uint32_t)tmp[w]);
+            tmp[16] = m < (uint32_t)kLdsSortMax ? 1 : 0;
+        }
+        __syncthreads();
+        small_ints = tmp[16] != 0;
+        __syncthreads();
+    }
+    if (small_ints) {
+        constexpr int kWords = kLdsSortMax / 32;
+        uint32_t* bm = buf;                      // presence bitmap
+        uint32_t* pre = buf + kWords;            // marked values below each word
+        for (int w = tid; w < kWords; w += blockDim.x) bm[w] = 0u;
+        __syncthreads();
+        for (int i = tid; i < n; i += blockDim.x) {
+            const uint32_t v = metric_key(J, metric, i);
+            atomicOr(&bm[v >> 5], 1u << (v & 31u));
+        }
+        __syncthreads();
+        static_assert(kWords == kSortThreads, "one bitmap word per thread");
+        int total = 0;
+        const int below = block_exclusive_scan(__popc(bm[tid]), tmp, &total);
+        pre[tid] = (uint32_t)below;
+        __syncthreads();
+        int32_t* out = J.rank + (int64_t)metric * n;
+        for (int i = tid; i < n; i += blockDim.x) {
+            const uint32_t v = metric_key(J, metric, i);
+            out[i] = (int32_t)(pre[v >> 5] + __popc(bm[v >> 5] & ((1u << (v & 31u)) - 1u)));
+        }
+        return;
+    }
 
     for (int i = tid; i < P; i += blockDim.x) buf[i] = i < n ? metric_key(J, metric, i) : 0xFFFFFFFFu;
     __syncthreads();
