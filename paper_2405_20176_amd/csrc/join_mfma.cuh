@@ -486,7 +486,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 
 template <int D, int H>
 JoinFn join_mfma_pick_kc(int kc) {
-    constexpr bool w4 = D >= 7 && D <= 10;
+    // Four waves per SIMD: d = 7..10 (k <= 10), and the hierarchical walk at
+    // d <= 6, whose extra state would otherwise leave it three.
+    constexpr bool w4 = (D >= 7 && D <= 10) || (H && D <= 6);
     switch (kc) {
         case 0: return k_join_mfma<D, 0, H>;
         case 5: return w4 ? k_join_mfma_w4<D, 5, H> : k_join_mfma<D, 5, H>;

@@ -11,8 +11,13 @@
 //                       in rounds of 256; inside a round every wavefront ranks
 //                       its 64 elements among equal digits with 8 ballots, the
 //                       wavefronts' counts are scanned in LDS, so every element
-//                       lands at (chunk offset of its digit) + (equal digits
-//                       before it in the chunk): the pass is stable.
+//                       gets its place among the chunk's equal digits: the pass
+//                       is stable.  The chunk is first laid out in LDS in digit
+//                       order, then stored with consecutive threads on
+//                       consecutive elements, so each digit's run of the chunk
+//                       goes out as one contiguous span (stored straight from
+//                       the rounds, each round's elements would land on up to
+//                       256 runs, a few bytes per cache line).
 // Four passes sort 32-bit keys; an even number of passes leaves the result in
 // buffer 0.
 #include "snaps_internal.h"
@@ -76,8 +81,12 @@ __global__ __launch_bounds__(1024) void k_radix_scan(const SortSeg* segs) {
 
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const SortSeg* segs, const int32_t* chunk_prefix,
                                                                   int n_segs, int shift, int src) {
-    __shared__ int off[256];
+    __shared__ int off[256];                     // chunk-local start of each digit's run
+    __shared__ int goff[256];                    // global start of each digit's run of this chunk
     __shared__ int wcnt[kRadixThreads / 64][256];
+    __shared__ int tmp[17];
+    __shared__ uint32_t s_key[kRadixChunk];
+    __shared__ uint32_t s_val[kRadixChunk];
     const int b = blockIdx.x;
     const int s = find_segment(chunk_prefix, n_segs, b);
     const SortSeg g = segs[s];
@@ -85,20 +94,36 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const SortSeg* 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    off[tid] = g.hist[(int64_t)tid * g.nchunks + c];
     const uint32_t* kin = g.key[src];
     uint32_t* kout = g.key[src ^ 1];
     const uint32_t* vin = g.val[src];
     uint32_t* vout = g.val[src ^ 1];
     const int64_t base = (int64_t)c * kRadixChunk;
+    const int m = (int)min((int64_t)kRadixChunk, g.n - base);    // elements of this chunk
+    // The chunk's histogram (for the local run starts), from this pass's keys.
+    off[tid] = 0;
+    __syncthreads();
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int e = r * kRadixThreads + tid;
+        if (e < m) atomicAdd(&off[(kin[base + e] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    {
+        int total;
+        const int cnt = off[tid];
+        const int start = block_exclusive_scan(cnt, tmp, &total);
+        goff[tid] = g.hist[(int64_t)tid * g.nchunks + c] - start;   // global position = goff + local
+        off[tid] = start;
+    }
+    __syncthreads();
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int r = 0; r < kRadixRounds; ++r) {
 #pragma unroll
         for (int w = 0; w < kRadixThreads / 64; ++w) wcnt[w][tid] = 0;
         __syncthreads();
-        const int64_t i = base + r * kRadixThreads + tid;
-        const bool valid = i < g.n;
-        const uint32_t key = valid ? kin[i] : 0u;
+        const int e = r * kRadixThreads + tid;
+        const bool valid = e < m;
+        const uint32_t key = valid ? kin[base + e] : 0u;
         const uint32_t digit = (key >> shift) & 255u;
         unsigned long long match = __ballot(valid);
 #pragma unroll
@@ -121,11 +146,18 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const SortSeg* 
         }
         __syncthreads();
         if (valid) {
-            const int dst = wcnt[wave][digit] + rank;
-            kout[dst] = key;
-            if (vin) vout[dst] = vin[i];
+            const int at = wcnt[wave][digit] + rank;   // chunk-local position in digit order
+            s_key[at] = key;
+            if (vin) s_val[at] = vin[base + e];
         }
         __syncthreads();
+    }
+    // Digit-ordered chunk out: local position p of digit d goes to goff[d] + p.
+    for (int p = tid; p < m; p += kRadixThreads) {
+        const uint32_t key = s_key[p];
+        const int dst = goff[(key >> shift) & 255u] + p;
+        kout[dst] = key;
+        if (vin) vout[dst] = s_val[p];
     }
 }
 
