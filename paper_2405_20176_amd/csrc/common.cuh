@@ -18,6 +18,10 @@ __device__ __forceinline__ cptr<T> as_const(const T* p) {
     return (cptr<T>)(p);
 }
 
+// v_writelane_b32: lane `lane` of the result takes `val` (wavefront-uniform),
+// every other lane keeps `old`.
+__device__ int lane_write(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 __device__ __forceinline__ float wave_min(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));

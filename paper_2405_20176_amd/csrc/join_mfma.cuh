@@ -3,33 +3,52 @@
 // k_join with one wavefront per workgroup and one query per lane; what
 // changes is how a (query tile, candidate tile) pair is screened.
 //
-// The prefilter test of query i and candidate j is h_j + q_i . p_j >= lim_i
-// (h_j = -pn_j (1 - c0) / 2 stored in the candidate's row, lim_i from
-// xf_limit).  For a 64 x 64 tile pair the scores h_j + q_i . p_j - lim_i are
-// a dense contraction, computed by v_mfma_f32_32x32x2f32 in four 32 x 32
-// blocks over ceil(d / 2) + 1 K-steps: the coordinates, then one step whose
-// two K slots carry (-lim_i, 1) and (1, h_j).  A pair passes when its
-// accumulator is >= 0.  For odd d the coordinate steps' pad slot carries
-// (-lim_i, 1) instead and the test is accumulator >= -h_j.  The rounding of that accumulation, with |lim_i|
-// among the summed magnitudes, stays inside the prefilter's margin (the
-// margin also allows products and sums that round separately), so every
-// candidate the exact direct form would accept still passes.
+// Prefilter.  A candidate j can matter to query i only if
+//     q_i . p_j - L_i >= -h_j,
+// with h_j = -pn_j (1 - c0) / 2 stored in the candidate's row and L_i the
+// query's limit (f16_limit).  The left side is a dense contraction over a
+// 64 x 64 tile pair, computed by v_mfma_f32_32x32x16_f16 in four 32 x 32
+// blocks.  Each float32 coordinate x is split into two half-precision pieces
+// x = xh + xl + e (xh = x rounded toward zero, xl = the exact float32
+// remainder rounded toward zero, |e| <= 2^-20 |x| + 2^-24), and the product
+// q_f p_f is taken as qh ph + qh pl + ql ph (three K slots; the dropped
+// ql pl is below 2^-20 |q_f p_f|).  -L_i enters as two more slots (its two
+// pieces times 1).  Half-precision products are exact in float32; the
+// matrix core's accumulation may drop low-order bits of the smaller products
+// (measured: products 2^-25 below the largest term vanish), which the limit
+// bounds as at most 2^-22 of the summed magnitudes per product.  h_j is not
+// a slot: the accumulator is compared with -h_j, per candidate column, in
+// float32.  f16_limit widens the exact limit by the sum of these bounds, so
+// every candidate that the direct form accepts passes; the rest of the
+// derivation (norms, direct form) is the one of xf_limit.
 //
-// Operand layouts (32 x 32 x 2, one block): lane l holds A[l % 32][l / 32]
-// and B[l / 32][l % 32]; accumulator register r of lane l is element
-// (8 (r / 4) + 4 (l / 32) + r % 4, l % 32).  Rows are queries, columns
-// candidates.  Most tile pairs have no passing pair, which a per-lane
-// maximum over the accumulators and one ballot establish.  Otherwise the
-// ballot of each accumulator register gives, in its low and high 32 bits,
-// the passing candidates of two queries in one candidate block; those bits
-// are written into the owning lanes' per-query candidate masks.  The tile's
+// The pieces need |x| <= 32 (half-precision range, with the limit clamped
+// to -30000, below every score such coordinates can produce).  A query tile
+// or a candidate tile with a coordinate outside that range is not screened:
+// every pair of it goes to the exact re-evaluation.
+//
+// Operand layout (32 x 32 x 16, one block; checked on the device): lane l
+// holds A[l % 32][8 (l / 32) + e] and B[8 (l / 32) + e][l % 32], e = 0..7,
+// as 4 registers of two halves each; accumulator register r of lane l is
+// element (8 (r / 4) + 4 (l / 32) + r % 4, l % 32).  Rows are queries,
+// columns candidates.  Lane half h carries coordinates [h M, h M + M) of its
+// row or column (M = ceil(d / 2); for odd d the last one of half 1 is 0).
+// Per pair of coordinates (a, b) three registers: A = (qh_a, qh_b), (qh_a,
+// qh_b), (ql_a, ql_b) against B = (ph_a, ph_b), (pl_a, pl_b), (ph_a, ph_b);
+// an odd M ends with A = (qh_c, qh_c), (ql_c, -L piece) against B = (ph_c,
+// pl_c), (ph_c, 1), the piece being -Lh in half 0 and -Ll in half 1; an even
+// M ends with A = (-Lh, -Ll) (half 0) or 0 (half 1) against B = (1, 1).
+//
+// Screening.  Most tile pairs have no passing pair, which a per-lane maximum
+// over the accumulators and one ballot establish.  Otherwise the ballot of
+// each accumulator register gives, in its low and high 32 bits, the passing
+// candidates of two queries in one candidate block; those bits are written
+// into the owning lanes' per-query candidate masks.  The tile's float32
 // candidate rows go from the operand registers into LDS, and each lane walks
 // its own mask in ascending candidate order: it re-evaluates the exact
 // direct-form distance of each candidate and updates its query's kNN list
 // and eps sums exactly as k_join does, in the same order, so the results
-// are identical to both k_join flavours.  (A wavefront-uniform walk over the
-// union of the masks costs one iteration per distinct candidate; the
-// per-lane walk costs the largest per-query count.)
+// are identical to both k_join flavours.
 //
 // Two walks (template parameter H).  H = 0 visits the candidate tiles in the
 // order of walk_tile and skips a tile whose box no query can reach; the
@@ -54,6 +73,8 @@ namespace snaps {
 namespace mfma_detail {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
 // Row (within the 64-query tile) of accumulator register r of block row rb
 // in lane half h.
@@ -61,6 +82,127 @@ __device__ __forceinline__ constexpr int acc_row(int rb, int r, int h) {
     return 32 * rb + 8 * (r >> 2) + 4 * h + (r & 3);
 }
 
+// Register plan of one lane half: M coordinates, their pairs, an odd one
+// left over, the registers that hold them and the K = 16 steps that take
+// those registers four at a time.
+template <int D>
+struct Split {
+    static constexpr int M = (D + 1) / 2;
+    static constexpr int PAIRS = M / 2;
+    static constexpr bool SINGLE = M % 2 == 1;
+    static constexpr int WORDS = 3 * PAIRS + (SINGLE ? 2 : 1);
+    static constexpr int NS = (WORDS + 3) / 4;
+    static constexpr int NW = 4 * NS;
+    // Limit widening: relative part c16 (qn + thr), absolute part cabs.
+    static constexpr float c16 = (float)(139 * NS + 120 + D) * 5.9604644775390625e-8f;
+    static constexpr float cabs = (float)(D + 8) * 5.9604644775390625e-8f;
+};
+
+// Largest coordinate magnitude the half-precision pieces take.
+constexpr float kF16Range = 32.f;
+constexpr unsigned kOnes16 = 0x3C003C00u;   // (1, 1) in half precision
+
+// Two floats rounded toward zero to half precision, packed low | high.
+__device__ __forceinline__ unsigned pk(float a, float b) {
+    return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(a, b));
+}
+__device__ __forceinline__ float lo_f(unsigned w) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xFFFFu));
+}
+__device__ __forceinline__ float hi_f(unsigned w) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+}
+
+// Lower limit L of q . p over the candidates that can still matter to a query
+// (see the file comment): the exact limit (qn - thr) / 2 of xf_limit widened
+// by c16 (qn + thr) + cabs, clamped to -30000 (every score of in-range
+// coordinates is above it, so a lower limit would pass the same pairs).
+template <int D>
+__device__ __forceinline__ float f16_limit(float qn, float thr) {
+    const float l = fmaf(-Split<D>::c16, qn + thr, 0.5f * (qn - thr)) - Split<D>::cabs;
+    return fmaxf(l, -30000.f);
+}
+
+// Register j of an operand held as NS groups of four (one per K step).
+template <int NS>
+__device__ __forceinline__ unsigned& word(u4v (&w)[NS], int j) {
+    return reinterpret_cast<unsigned*>(&w[j >> 2])[j & 3];
+}
+
+// Candidate-side registers from this lane half's M float32 coordinates.
+template <int D>
+__device__ __forceinline__ void b_words(const float (&v)[Split<D>::M], u4v (&wv)[Split<D>::NS]) {
+    using S = Split<D>;
+    unsigned w[S::NW];
+#pragma unroll
+    for (int j = 0; j < S::PAIRS; ++j) {
+        const float a = v[2 * j], b = v[2 * j + 1];
+        const unsigned h = pk(a, b);
+        w[3 * j] = h;
+        w[3 * j + 1] = pk(a - lo_f(h), b - hi_f(h));
+        w[3 * j + 2] = h;
+    }
+    if constexpr (S::SINGLE) {
+        const float c = v[S::M - 1];
+        const unsigned h1 = pk(c, 1.f);
+        w[3 * S::PAIRS] = pk(c, c - lo_f(h1));
+        w[3 * S::PAIRS + 1] = h1;
+    } else {
+        w[3 * S::PAIRS] = kOnes16;
+    }
+#pragma unroll
+    for (int j = S::WORDS; j < S::NW; ++j) w[j] = 0u;
+#pragma unroll
+    for (int i = 0; i < S::NS; ++i) wv[i] = u4v{w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]};
+}
+
+// Query-side registers (without the limit pieces, which limit_words sets);
+// for an odd M, rq = the float32 remainder of the odd coordinate.
+template <int D>
+__device__ __forceinline__ void a_words(const float (&v)[Split<D>::M], u4v (&wv)[Split<D>::NS], float& rq) {
+    using S = Split<D>;
+    unsigned w[S::NW];
+#pragma unroll
+    for (int j = 0; j < S::PAIRS; ++j) {
+        const float a = v[2 * j], b = v[2 * j + 1];
+        const unsigned h = pk(a, b);
+        w[3 * j] = h;
+        w[3 * j + 1] = h;
+        w[3 * j + 2] = pk(a - lo_f(h), b - hi_f(h));
+    }
+    rq = 0.f;
+    if constexpr (S::SINGLE) {
+        const float c = v[S::M - 1];
+        const unsigned h1 = pk(c, c);
+        w[3 * S::PAIRS] = h1;
+        rq = c - lo_f(h1);
+        w[3 * S::PAIRS + 1] = 0u;
+    } else {
+        w[3 * S::PAIRS] = 0u;
+    }
+#pragma unroll
+    for (int j = S::WORDS; j < S::NW; ++j) w[j] = 0u;
+#pragma unroll
+    for (int i = 0; i < S::NS; ++i) wv[i] = u4v{w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]};
+}
+
+// The limit pieces of one block row's query (lim = L of that row): -Lh =
+// -L rounded toward zero, -Ll = the float32 remainder rounded toward zero.
+template <int D>
+__device__ __forceinline__ void limit_words(float lim, int half, float rq, u4v (&w)[Split<D>::NS]) {
+    using S = Split<D>;
+    const float nl = -lim;
+    const float nlh = lo_f(pk(nl, 0.f));
+    const float r = nl - nlh;
+    if constexpr (S::SINGLE)
+        word(w, 3 * S::PAIRS + 1) = pk(rq, half ? r : nl);
+    else
+        word(w, 3 * S::PAIRS) = half ? 0u : pk(nl, r);
+}
+
+__device__ __forceinline__ h8v op(const u4v& w) {
+    return __builtin_bit_cast(h8v, w);
+}
 
 }  // namespace mfma_detail
 
@@ -69,16 +211,11 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
     using namespace mfma_detail;
     constexpr int DP = row_stride(D);
     constexpr int KS = KC > 0 ? KC : 1;
-    constexpr int KSTEPS = (D + 1) / 2;      // coordinate steps
-    // Even d: one more step carries (-lim_i, 1) and (1, h_j), and a pair
-    // passes when its score is >= 0.  Odd d: the pad slot of the last
-    // coordinate step carries (-lim_i, 1), and h_j moves into the comparison
-    // (score >= -h_j, exact), which saves that step.
-    constexpr bool kFold = D % 2 == 1;
-    constexpr int NSTEP = kFold ? KSTEPS : KSTEPS + 1;
-    constexpr float cq = (float)(2 * (8 * D + 24)) * 5.9604644775390625e-8f;
+    using S = Split<D>;
+    constexpr int M = S::M;                  // coordinates per lane half
+    constexpr int NS = S::NS;                // K = 16 steps per block
+    constexpr int NW = S::NW;                // operand registers per lane
     __shared__ int s_unit, s_queue;
-    __shared__ uint2 s_mask[64];            // per-query candidate masks of one tile pair
     __shared__ __align__(16) float s_cand[64][DP];   // candidate rows of a tile pair with passes
     // Walk entries: tile index | the 32 x 32 blocks (query block row rb,
     // candidate half cb) that may hold a pair in reach, bit rb + 2 cb, << 26
@@ -88,7 +225,6 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
 
     const int lane = threadIdx.x;
     const int half = lane >> 5;
-    s_mask[lane] = make_uint2(0u, 0u);
     const int col = lane & 31;
     const int home = blockIdx.x % kQueues;
     unsigned drained = 0;
@@ -127,33 +263,36 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
         float qn = 0.f;
 #pragma unroll
         for (int f = 0; f < D; ++f) qn = fmaf(q[f], q[f], qn);
-        float lim = xf_limit(qn, thr, cq);
+        float lim = f16_limit<D>(qn, thr);
         const int nq = max(0, min(kTile, n - t0 * kTile));
         long long pairs = 0;
         int scanned = 0, skipped = 0;
 
-        // A operands: query rows 32 rb + col of the tile, dimensions 2 s + half
-        // (pad rows beyond n hold NaN and never pass; a pad dimension is 0),
-        // then (-lim, 1) of the same query.
-        float av[2][KSTEPS + 1];
+        // A operands: query rows 32 rb + col of the tile, this lane half's
+        // coordinates (pad rows beyond n hold NaN and never pass), then the
+        // limit pieces of the same query.  A query tile with a coordinate out
+        // of the pieces' range is not screened (every pair is re-evaluated).
+        u4v aw[2][NS];
+        float rq[2];
+        bool unit_all;
+        {
+            float amax = 0.f;
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-            const float* rowp = xs_g + (int64_t)(t0 * kTile + 32 * rb + col) * DP + half;
+            for (int rb = 0; rb < 2; ++rb) {
+                const float* rowp = xs_g + (int64_t)(t0 * kTile + 32 * rb + col) * DP + half * M;
+                float v[M];
 #pragma unroll
-            for (int s = 0; s < KSTEPS; ++s) {
-                const float v = rowp[2 * s];
-                av[rb][s] = (kFold && s == KSTEPS - 1 && half) ? 0.f : v;
+                for (int i = 0; i < M; ++i) {
+                    v[i] = (D % 2 == 1 && i == M - 1 && half) ? 0.f : rowp[i];
+                    amax = fmaxf(amax, fabsf(v[i]));
+                }
+                a_words<D>(v, aw[rb], rq[rb]);
             }
+            unit_all = __any(amax > kF16Range);
         }
         auto refresh_limits = [&]() {
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                const float l = __shfl(lim, 32 * rb + col, 64);
-                if (kFold)
-                    av[rb][KSTEPS - 1] = half ? -l : av[rb][KSTEPS - 1];
-                else
-                    av[rb][KSTEPS] = half ? 1.f : -l;
-            }
+            for (int rb = 0; rb < 2; ++rb) limit_words<D>(__shfl(lim, 32 * rb + col, 64), half, rq[rb], aw[rb]);
         };
         refresh_limits();
 
@@ -184,7 +323,7 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
                 const float nthr = fmaxf(kd[KS - 1], eps2);
                 const bool moved = nthr != thr;
                 thr = nthr;
-                lim = xf_limit(qn, thr, cq);
+                lim = f16_limit<D>(qn, thr);
                 return moved;
             }
             return false;
@@ -269,23 +408,22 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
                 }
             }
         };
-        // Raw B operands of tile t (candidate rows 32 cb + col: lane half 0
-        // reads the even dimensions, half 1 the odd ones, then h), loaded
-        // through the global address space so that the loads are waited on
-        // only where the values are used, one tile later.
+        // Candidate rows of tile t (rows 32 cb + col): this lane half's
+        // coordinates, then h and the id, loaded through the global address
+        // space so that the loads are waited on only where the values are
+        // used, one tile later.  The id comes along so that the exact
+        // recheck can stage whole candidate rows from these registers.
         typedef const __attribute__((address_space(1))) float* gfloat;
         const gfloat xg = (gfloat)xs_g;
-        // The candidate's id bits come along, so that the exact recheck can
-        // stage whole candidate rows from these registers.
-        auto load_b = [&](int tv, float (&br)[2][KSTEPS + 2]) {
+        auto load_b = [&](int tv, float (&br)[2][M + 2]) {
             const int t = tv & kTileMask;
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                const gfloat rowc = xg + (int64_t)(t * kTile + 32 * cb + col) * DP + half;
+                const gfloat rowc = xg + (int64_t)(t * kTile + 32 * cb + col) * DP;
 #pragma unroll
-                for (int s2 = 0; s2 < KSTEPS; ++s2) br[cb][s2] = rowc[2 * s2];
-                br[cb][KSTEPS] = rowc[D - half];
-                br[cb][KSTEPS + 1] = rowc[D + 1 - half];
+                for (int i = 0; i < M; ++i) br[cb][i] = rowc[half * M + i];
+                br[cb][M] = rowc[D];
+                br[cb][M + 1] = rowc[D + 1];
             }
         };
 
@@ -294,7 +432,7 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
         // and its operands requested before the current tile is screened.
         // Two operand buffers, used alternately (no copies between them, so a
         // tile's loads are waited on only when that tile is screened).
-        auto process = [&](int tv, float (&br)[2][KSTEPS + 2]) {
+        auto process = [&](int tv, float (&br)[2][M + 2]) {
             const int t = tv & kTileMask;
             const int blocks = tv >> kRowShift;
             const int rows = (blocks | (blocks >> 2)) & 3;
@@ -310,92 +448,71 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
             }
             const int cbase = t * kTile;
 
-            // B operands in place: 0 in the pad slot of an odd d, then (1, h)
-            // (the exact recheck reads only the coordinates and the id).
+            // One 32 x 32 block at a time (the candidate half's registers and
+            // one block's accumulators live): its scores, a screen (most
+            // blocks have no passing pair), then the ballots, whose low and
+            // high halves go to the owning queries' lanes of the candidate
+            // masks mk (one per candidate half).
+            bool hit = false, all = unit_all;
+            unsigned mk[2] = {0u, 0u};
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                if (kFold)
-                    br[cb][KSTEPS - 1] = half ? 1.f : br[cb][KSTEPS - 1];
-                else
-                    br[cb][KSTEPS] = half ? br[cb][KSTEPS] : 1.f;
-            }
-            // Pass threshold of this lane's candidate column in each block.
-            const float nh0 = kFold ? -br[0][KSTEPS] : 0.f;
-            const float nh1 = kFold ? -br[1][KSTEPS] : 0.f;
-            // One block row of queries at a time (32 accumulators live): the
-            // scores, a screen (most tile pairs have no passing pair), then the
-            // ballots, whose low and high halves lane 0 writes into the owning
-            // queries' rows of an LDS table of candidate masks.
-            unsigned u_lo = 0, u_hi = 0;
+                // H = 1: a block row out of reach of this candidate half is
+                // not contracted; its scores never pass.
+                const int act = H ? ((blocks >> (2 * cb)) & 3) : rows;
+                if (!act) continue;
+                float v[M];
+                float cmax = 0.f;
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                if (!((rows >> rb) & 1)) continue;
-                // H = 1: a candidate half out of reach of this block row is
-                // not contracted (both chains otherwise, interleaved on the
-                // matrix pipe); its scores never pass.
-                const bool act0 = H ? ((blocks >> rb) & 1) != 0 : true;
-                const bool act1 = H ? ((blocks >> (rb + 2)) & 1) != 0 : true;
-                f16v acc[2];
-                if (act0 && act1) {
-#pragma unroll
-                    for (int cb = 0; cb < 2; ++cb) {
-                        acc[cb] = f16v{};
-#pragma unroll
-                        for (int s2 = 0; s2 < NSTEP; ++s2)
-                            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][s2], br[cb][s2], acc[cb], 0, 0, 0);
-                    }
-                } else {
-                    const int cb = act0 ? 0 : 1;
-                    acc[0] = f16v{};
-                    acc[1] = f16v{};
-                    f16v a1 = f16v{};
-#pragma unroll
-                    for (int s2 = 0; s2 < NSTEP; ++s2)
-                        a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][s2], cb ? br[1][s2] : br[0][s2], a1, 0, 0, 0);
-                    if (cb) acc[1] = a1; else acc[0] = a1;
+                for (int i = 0; i < M; ++i) {
+                    v[i] = (D % 2 == 1 && i == M - 1 && half) ? 0.f : br[cb][i];
+                    cmax = fmaxf(cmax, fabsf(v[i]));
                 }
-                float mx0 = -INFINITY, mx1 = -INFINITY;     // NaN pads never pass
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    mx0 = fmaxf(mx0, acc[0][r]);
-                    mx1 = fmaxf(mx1, acc[1][r]);
+                if (__any(cmax > kF16Range)) {
+                    all = true;
+                    continue;
                 }
-                if (!act0) mx0 = -INFINITY;
-                if (!act1) mx1 = -INFINITY;
-                if (!__any(mx0 >= nh0 || mx1 >= nh1)) continue;
+                u4v bw[NS];
+                b_words<D>(v, bw);
+                const float nh = -br[cb][M];      // pass threshold of this lane's candidate column
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const unsigned long long b0 = act0 ? __ballot(acc[0][r] >= nh0) : 0ull;
-                    const unsigned long long b1 = act1 ? __ballot(acc[1][r] >= nh1) : 0ull;
-                    if (b0 | b1) {
+                for (int rb = 0; rb < 2; ++rb) {
+                    if (!((act >> rb) & 1)) continue;
+                    f16v acc = f16v{};
+#pragma unroll
+                    for (int s2 = 0; s2 < NS; ++s2)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(op(aw[rb][s2]), op(bw[s2]), acc, 0, 0, 0);
+                    float mx = -INFINITY;     // NaN pads never pass
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) mx = fmaxf(mx, acc[r]);
+                    if (!__any(mx >= nh)) continue;
+                    hit = true;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const unsigned long long bm = __ballot(acc[r] >= nh);
                         const int i0 = acc_row(rb, r, 0);
-                        if (lane == 0) {
-                            s_mask[i0] = make_uint2((unsigned)b0, (unsigned)b1);
-                            s_mask[i0 + 4] = make_uint2((unsigned)(b0 >> 32), (unsigned)(b1 >> 32));
-                        }
-                        u_lo |= (unsigned)b0 | (unsigned)(b0 >> 32);
-                        u_hi |= (unsigned)b1 | (unsigned)(b1 >> 32);
+                        mk[cb] = (unsigned)lane_write((int)(unsigned)bm, i0, (int)mk[cb]);
+                        mk[cb] = (unsigned)lane_write((int)(unsigned)(bm >> 32), i0 + 4, (int)mk[cb]);
                     }
                 }
             }
-            if (u_lo | u_hi) {
-                const uint2 mine2 = s_mask[lane];
-                s_mask[lane] = make_uint2(0u, 0u);
+            if (hit || all) {
                 // The tile's candidate rows into LDS (row 32 cb + col: this
-                // lane's dimensions 2 s + half; the id from lane half 0), so
-                // that each lane reads the rows of its own passing candidates.
+                // lane half's coordinates; the id from lane half 0), so that
+                // each lane reads the rows of its own passing candidates.
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
                     float* row = &s_cand[32 * cb + col][0];
 #pragma unroll
-                    for (int s2 = 0; s2 < KSTEPS; ++s2)
-                        if (2 * s2 + half < D) row[2 * s2 + half] = br[cb][s2];
-                    if (!half) reinterpret_cast<int*>(row)[D] = __float_as_int(br[cb][KSTEPS + 1]);
+                    for (int i = 0; i < M; ++i)
+                        if (half * M + i < D) row[half * M + i] = br[cb][i];
+                    if (!half) reinterpret_cast<int*>(row)[D] = __float_as_int(br[cb][M + 1]);
                 }
                 bool moved = false;
                 // This lane's passing candidates in ascending order (block 0,
                 // then block 1): the order in which the direct form meets them.
-                unsigned long long mine = ((unsigned long long)mine2.y << 32) | mine2.x;
+                // A tile that was not screened offers every candidate.
+                unsigned long long mine = all ? ~0ull : (((unsigned long long)mk[1] << 32) | mk[0]);
                 while (mine) {
                     const int j = __builtin_ctzll(mine);
                     mine &= mine - 1;
@@ -416,7 +533,7 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
         // current tile) so that every path waits on the same load count.
         // A scheduling barrier after each prefetch keeps the compiler from
         // hoisting the other buffer's uses (and their waits) above it.
-        float ba[2][KSTEPS + 2], bb[2][KSTEPS + 2];
+        float ba[2][M + 2], bb[2][M + 2];
         int t = next_tile();
         load_b(t >= 0 ? t : t0, ba);
         while (t >= 0) {
@@ -486,9 +603,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 
 template <int D, int H>
 JoinFn join_mfma_pick_kc(int kc) {
-    // Four waves per SIMD: d = 7..10 (k <= 10), and the hierarchical walk at
-    // d <= 6, whose extra state would otherwise leave it three.
-    constexpr bool w4 = (D >= 7 && D <= 10) || (H && D <= 6);
+    constexpr bool w4 = false;
     switch (kc) {
         case 0: return k_join_mfma<D, 0, H>;
         case 5: return w4 ? k_join_mfma_w4<D, 5, H> : k_join_mfma<D, 5, H>;

@@ -167,6 +167,37 @@ def test_matrix_core_prefilter_every_d_and_k(S, d):
         check_scores(b, run_oracle(x, mask, k, eps), k, eps, label=f"matrix cores d={d} k={k}")
 
 
+@pytest.mark.parametrize("case", ["beyond_range", "some_beyond_range", "tiny_scale", "offset_negative"])
+@pytest.mark.parametrize("d", [3, 8, 15])
+def test_matrix_core_half_precision_range(S, case, d):
+    """The matrix cores screen with half-precision pieces of coordinates up to
+    32 in magnitude: populations beyond that (all of them, or a few objects
+    in some tiles) take the exact re-evaluation for the affected tiles,
+    coordinates near the half-precision subnormal range and populations far
+    from the origin keep a valid limit.  Outputs equal the direct form's bit
+    for bit and meet the oracle."""
+    rng = np.random.default_rng(["beyond_range", "some_beyond_range", "tiny_scale", "offset_negative"].index(case) * 31 + d)
+    n = 3000
+    x = rng.random((n, 16)).astype(np.float32)
+    if case == "beyond_range":
+        x = (x * 200.0 - 50.0).astype(np.float32)
+    elif case == "some_beyond_range":
+        x[rng.choice(n, 5, replace=False)] *= np.float32(100.0)
+    elif case == "tiny_scale":
+        x = (x * 3e-6).astype(np.float32)
+    else:
+        x = (x * 0.5 - 31.0).astype(np.float32)
+    mask = (1 << d) - 1
+    xs = O.project(x, mask).astype(np.float32)
+    eps = float(O.eps_exact_mean_count(xs, 10))
+    k = 10
+    a = run_gpu(S, x, mask, k, eps, S.tuning(split=1, filter=1))
+    m = run_gpu(S, x, mask, k, eps, S.tuning(split=1, filter=3))
+    for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+        np.testing.assert_array_equal(a[key], m[key], err_msg=f"{key} {case} d={d}")
+    check_scores(m, run_oracle(x, mask, k, eps), k, eps, label=f"half-precision range {case} d={d}")
+
+
 @pytest.mark.parametrize("d", [2, 5, 8, 12])
 def test_index_sorts_agree(S, d):
     """The packed-key LDS index and the full-key device-wide index order the
