@@ -22,6 +22,20 @@ __device__ __forceinline__ cptr<T> as_const(const T* p) {
 // every other lane keeps `old`.
 __device__ int lane_write(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
+// Waits written as asm with a memory clobber, so that the compiler neither
+// moves memory accesses across them nor keeps LDS values in registers
+// across them: at most N vector memory operations of this wavefront still
+// outstanding (global-to-LDS copies included, which the compiler does not
+// track), and all LDS operations complete.
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+    static_assert(N >= 0 && N < 16, "vmcnt field");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void wait_lds() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
 __device__ __forceinline__ float wave_min(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));

@@ -216,7 +216,12 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
     constexpr int NS = S::NS;                // K = 16 steps per block
     constexpr int NW = S::NW;                // operand registers per lane
     __shared__ int s_unit, s_queue;
-    __shared__ __align__(16) float s_cand[64][DP];   // candidate rows of a tile pair with passes
+    // Candidate rows of two tiles (the one screened and the next), copied
+    // from global memory straight into LDS.  Two separate arrays, each named
+    // at compile time wherever it is used, so that the compiler can tell a
+    // read of one from the copy in flight into the other.
+    __shared__ __align__(16) float s_rows0[kTile * DP];
+    __shared__ __align__(16) float s_rows1[kTile * DP];
     // Walk entries: tile index | the 32 x 32 blocks (query block row rb,
     // candidate half cb) that may hold a pair in reach, bit rb + 2 cb, << 26
     // (H = 0 sets both halves of a block row together).
@@ -408,23 +413,19 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
                 }
             }
         };
-        // Candidate rows of tile t (rows 32 cb + col): this lane half's
-        // coordinates, then h and the id, loaded through the global address
-        // space so that the loads are waited on only where the values are
-        // used, one tile later.  The id comes along so that the exact
-        // recheck can stage whole candidate rows from these registers.
+        // The 64 rows of tile t into LDS buffer `buf`: DP / 4 copies of 16
+        // bytes per lane, global memory to LDS without registers.  The LDS
+        // reads of the buffer's previous tile are complete first.
         typedef const __attribute__((address_space(1))) float* gfloat;
         const gfloat xg = (gfloat)xs_g;
-        auto load_b = [&](int tv, float (&br)[2][M + 2]) {
+        auto load_rows = [&](int tv, float* dst) {
             const int t = tv & kTileMask;
+            const gfloat src = xg + (int64_t)t * kTile * DP + lane * 4;
+            wait_lds();
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                const gfloat rowc = xg + (int64_t)(t * kTile + 32 * cb + col) * DP;
-#pragma unroll
-                for (int i = 0; i < M; ++i) br[cb][i] = rowc[half * M + i];
-                br[cb][M] = rowc[D];
-                br[cb][M + 1] = rowc[D + 1];
-            }
+            for (int i = 0; i < DP / 4; ++i)
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + i * 256),
+                                                 (__attribute__((address_space(3))) void*)(dst + i * 256), 16, 0, 0);
         };
 
         // Software pipeline: the next tile is chosen (with the threshold as
@@ -432,7 +433,7 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
         // and its operands requested before the current tile is screened.
         // Two operand buffers, used alternately (no copies between them, so a
         // tile's loads are waited on only when that tile is screened).
-        auto process = [&](int tv, float (&br)[2][M + 2]) {
+        auto process = [&](int tv, const float* rows_l) {
             const int t = tv & kTileMask;
             const int blocks = tv >> kRowShift;
             const int rows = (blocks | (blocks >> 2)) & 3;
@@ -461,11 +462,14 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
                 // not contracted; its scores never pass.
                 const int act = H ? ((blocks >> (2 * cb)) & 3) : rows;
                 if (!act) continue;
+                // This lane's candidate (row 32 cb + col): its half's
+                // coordinates and h.
+                const float* rowc = rows_l + (32 * cb + col) * DP;
                 float v[M];
                 float cmax = 0.f;
 #pragma unroll
                 for (int i = 0; i < M; ++i) {
-                    v[i] = (D % 2 == 1 && i == M - 1 && half) ? 0.f : br[cb][i];
+                    v[i] = (D % 2 == 1 && i == M - 1 && half) ? 0.f : rowc[half * M + i];
                     cmax = fmaxf(cmax, fabsf(v[i]));
                 }
                 if (__any(cmax > kF16Range)) {
@@ -474,7 +478,7 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
                 }
                 u4v bw[NS];
                 b_words<D>(v, bw);
-                const float nh = -br[cb][M];      // pass threshold of this lane's candidate column
+                const float nh = -rowc[D];        // pass threshold of this lane's candidate column
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
                     if (!((act >> rb) & 1)) continue;
@@ -497,17 +501,6 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
                 }
             }
             if (hit || all) {
-                // The tile's candidate rows into LDS (row 32 cb + col: this
-                // lane half's coordinates; the id from lane half 0), so that
-                // each lane reads the rows of its own passing candidates.
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
-                    float* row = &s_cand[32 * cb + col][0];
-#pragma unroll
-                    for (int i = 0; i < M; ++i)
-                        if (half * M + i < D) row[half * M + i] = br[cb][i];
-                    if (!half) reinterpret_cast<int*>(row)[D] = __float_as_int(br[cb][M + 1]);
-                }
                 bool moved = false;
                 // This lane's passing candidates in ascending order (block 0,
                 // then block 1): the order in which the direct form meets them.
@@ -517,35 +510,41 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
                     const int j = __builtin_ctzll(mine);
                     mine &= mine - 1;
                     if (cbase + j == qpos) continue;
-                    const float* row = &s_cand[j][0];
+                    const float* row = rows_l + j * DP;
                     float dd = 0.f;
 #pragma unroll
                     for (int f = 0; f < D; ++f) {
                         const float tq = q[f] - row[f];
                         dd = fmaf(tq, tq, dd);
                     }
-                    if (dd <= thr) moved |= take(dd, reinterpret_cast<const int*>(row)[D]);
+                    if (dd <= thr) moved |= take(dd, reinterpret_cast<const int*>(row)[D + 1]);
                 }
                 if (__any(moved)) refresh_limits();
             }
         };
-        // The loads are issued unconditionally (the last prefetch re-reads the
-        // current tile) so that every path waits on the same load count.
-        // A scheduling barrier after each prefetch keeps the compiler from
-        // hoisting the other buffer's uses (and their waits) above it.
-        float ba[2][M + 2], bb[2][M + 2];
+        // The rows of the next tile are requested before the current tile is
+        // screened; the wait leaves those DP / 4 copies in flight.  The last
+        // tile waits for everything, so no copy outlives the unit.
         int t = next_tile();
-        load_b(t >= 0 ? t : t0, ba);
+        if (t >= 0) load_rows(t, s_rows0);
         while (t >= 0) {
-            const int tn = next_tile();
-            load_b(tn >= 0 ? tn : t, bb);
-            __builtin_amdgcn_sched_barrier(0);
-            process(t, ba);
+            int tn = next_tile();
+            if (tn >= 0) {
+                load_rows(tn, s_rows1);
+                wait_vmem<DP / 4>();
+            } else {
+                wait_vmem<0>();
+            }
+            process(t, s_rows0);
             if (tn < 0) break;
             t = next_tile();
-            load_b(t >= 0 ? t : tn, ba);
-            __builtin_amdgcn_sched_barrier(0);
-            process(tn, bb);
+            if (t >= 0) {
+                load_rows(t, s_rows0);
+                wait_vmem<DP / 4>();
+            } else {
+                wait_vmem<0>();
+            }
+            process(tn, s_rows1);
         }
 
         if (A.stats && lane == 0) {
