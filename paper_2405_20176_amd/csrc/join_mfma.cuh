@@ -338,11 +338,14 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
         // -1 at the end), in the order of walk_tile; bits 26-29 of the result
         // flag the 32 x 32 blocks with a query that may reach the candidates
         // (the other blocks' contractions are skipped).
+        // (q - clamp(q, lo, hi) is the signed gap, the subtraction that the
+        // direct form makes with the nearest box corner, so it rounds the
+        // same way.)
         auto reach_of = [&](cptr<float> bx) -> unsigned long long {
             float lb = 0.f;
 #pragma unroll
             for (int f = 0; f < D; ++f) {
-                const float g = fmaxf(fmaxf(bx[f] - q[f], q[f] - bx[DP + f]), 0.f);
+                const float g = q[f] - __builtin_amdgcn_fmed3f(q[f], bx[f], bx[DP + f]);
                 lb = fmaf(g, g, lb);
             }
             return __ballot(lb <= thr);
