@@ -594,23 +594,23 @@ __global__ __launch_bounds__(64) void k_join_mfma(JoinArgs A) {
     join_mfma_body<D, KC, H>(A);
 }
 
-// The same kernel held to 128 VGPRs, four wavefronts per SIMD instead of
-// three.
+// The same kernel held to 96 VGPRs, five wavefronts per SIMD instead of
+// four (at d = 5..10 it spills 4-10 registers and is still about 10 %
+// faster; held to 80 for six, it spills 20-40 and is 25-55 % slower).
 template <int D, int KC, int H>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_join_mfma_w4(JoinArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_join_mfma_w5(JoinArgs A) {
     join_mfma_body<D, KC, H>(A);
 }
 
 template <int D, int H>
 JoinFn join_mfma_pick_kc(int kc) {
-    // Four waves per SIMD for d = 7..10: it spills a few registers and is
-    // still 15-20 % faster there (measured per d over all SNAPShot1-shaped
-    // subspaces of that d).
-    constexpr bool w4 = D >= 7 && D <= 10;
+    // Five waves per SIMD for d = 5..10 (measured per d over all
+    // SNAPShot1-shaped subspaces of that d).
+    constexpr bool w5 = D >= 5 && D <= 10;
     switch (kc) {
         case 0: return k_join_mfma<D, 0, H>;
-        case 5: return w4 ? k_join_mfma_w4<D, 5, H> : k_join_mfma<D, 5, H>;
-        case 10: return w4 ? k_join_mfma_w4<D, 10, H> : k_join_mfma<D, 10, H>;
+        case 5: return w5 ? k_join_mfma_w5<D, 5, H> : k_join_mfma<D, 5, H>;
+        case 10: return w5 ? k_join_mfma_w5<D, 10, H> : k_join_mfma<D, 10, H>;
         case 20: return k_join_mfma<D, 20, H>;
         case 32: return k_join_mfma<D, 32, H>;
     }
