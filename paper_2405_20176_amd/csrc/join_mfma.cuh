@@ -604,9 +604,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 5))) void
 
 template <int D, int H>
 JoinFn join_mfma_pick_kc(int kc) {
-    // Five waves per SIMD for d = 5..10 (measured per d over all
-    // SNAPShot1-shaped subspaces of that d).
-    constexpr bool w5 = D >= 5 && D <= 10;
+    // Five waves per SIMD for the lean walk at d = 5..10 (measured per d over
+    // all SNAPShot1-shaped subspaces of that d); the hierarchical walk would
+    // spill 14-35 registers there and keeps four.
+    constexpr bool w5 = H == 0 && D >= 5 && D <= 10;
     switch (kc) {
         case 0: return k_join_mfma<D, 0, H>;
         case 5: return w5 ? k_join_mfma_w5<D, 5, H> : k_join_mfma<D, 5, H>;
