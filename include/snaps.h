@@ -129,7 +129,9 @@ typedef struct {
     int32_t filter;         /* 0 auto (3), 1 direct distance form only,
                                2 expanded-form prefilter on the vector ALU with exact direct
                                recheck, 3 the same prefilter as a dense contraction on the
-                               matrix cores (MFMA), exact direct recheck; with split or mq
+                               matrix cores (fp16 MFMA over each coordinate split into two
+                               fp16 pieces, limit widened by the split and accumulation
+                               bounds), exact direct recheck; with split or mq
                                above 1 the vector-ALU prefilter runs instead.  All give
                                identical results. */
     int32_t passes;         /* 0 = all; else a mask of SNAPS_PASS_*.  A call that runs the join
