@@ -578,10 +578,12 @@ def _cpu_model():
     return "unknown"
 
 
-def per_d_breakdown(lib, S, jobs, dims, n, k, dev, stream, out_cnt):
+def per_d_breakdown(lib, S, jobs, dims, n, k, dev, stream, out_cnt, filt=0):
     """One eager index + join pass per dimensionality with its own counters
     and HIP events (after the timed steps): join time, pairs evaluated,
-    candidates per result and the fraction of the fp32 peak, per d."""
+    candidates per result and the fraction of the fp32 peak, per d.  filt
+    selects the per-pair test (0 default, 2 prefilter on the vector ALU,
+    3 on the matrix cores)."""
     import torch
     sptr = ctypes.c_void_p(stream.cuda_stream)
     out = {}
@@ -591,7 +593,7 @@ def per_d_breakdown(lib, S, jobs, dims, n, k, dev, stream, out_cnt):
         assert idx[-1] - s0 + 1 == cnt
         ptr = ctypes.cast(ctypes.byref(jobs, s0 * ctypes.sizeof(S.c_job)), ctypes.POINTER(S.c_job))
         st = torch.zeros(4, dtype=torch.int64, device=dev)
-        t_idx, t_join = S.tuning(passes=S.PASS_INDEX), S.tuning(passes=S.PASS_JOIN, stats=st)
+        t_idx, t_join = S.tuning(passes=S.PASS_INDEX), S.tuning(passes=S.PASS_JOIN, stats=st, filter=filt)
         need = lib.snaps_outlier_scores_workspace(ptr, cnt, ctypes.byref(t_join))
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
         wsp = ctypes.c_void_p(ws.data_ptr())
@@ -659,6 +661,8 @@ def main():
                     help="subspaces in the eps-grid and k-grid slices")
     ap.add_argument("--no-per-d", dest="per_d", action="store_false",
                     help="skip the per-dimensionality join breakdown (one eager pass per d after the timed steps)")
+    ap.add_argument("--filter-ab", action="store_true",
+                    help="after the per-d breakdown, time each d's join with the prefilter on the vector ALU and on the matrix cores")
     ap.add_argument("--no-c2", dest="c2", action="store_false",
                     help="skip the LSST-scale population (5,000,000 objects, the full space + 105 two-feature spaces)")
     ap.add_argument("--c2-steps", type=int, default=1, help="timed steps of the LSST-scale population")
@@ -861,6 +865,15 @@ def main():
         result["join_per_d"] = per_d_breakdown(lib, S, jobs, dims, n, k, dev, stream, out_cnt)
         log("per d: " + ", ".join(f"d={d} {v['join_ms']:.0f} ms frac {v['frac']:.2f} pairs/bf {v['pairs_over_brute_force']:.2f}"
                                   for d, v in result["join_per_d"].items()))
+        if a.filter_ab:
+            # the same passes with the prefilter on the vector ALU, then on the
+            # matrix cores (identical results; the kernels differ)
+            ab = {f: per_d_breakdown(lib, S, jobs, dims, n, k, dev, stream, out_cnt, filt=f) for f in (2, 3)}
+            result["filter_ab_per_d"] = {
+                d: {"valu_prefilter_ms": ab[2][d]["join_ms"], "mfma_ms": ab[3][d]["join_ms"],
+                    "mfma_speedup": ab[2][d]["join_ms"] / ab[3][d]["join_ms"]} for d in ab[3]}
+            log("filter A/B (vector-ALU prefilter / matrix cores): " + ", ".join(
+                f"d={d} {v['valu_prefilter_ms']:.0f}/{v['mfma_ms']:.0f} ms" for d, v in result["filter_ab_per_d"].items()))
 
     if not a.no_plain:
         tune = S.tuning()
