@@ -201,7 +201,7 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
             cnt[r] = 0;
             sum[r] = 0.0;
             thr[r] = KC > 0 ? fmaxf(kd[r][KS - 1], eps2) : eps2;
-            if (t0 + r >= nt) thr[r] = -INFINITY;             // no query: every tile out of reach
+            if (qpos[r] >= n) thr[r] = -INFINITY;             // no query (pad lane or missing tile): nothing in reach
             qn[r] = 0.f;
 #pragma unroll
             for (int f = 0; f < D; ++f) qn[r] = fmaf(q[r][f], q[r][f], qn[r]);

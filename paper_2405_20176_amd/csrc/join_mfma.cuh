@@ -265,6 +265,7 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
         int cnt = 0;
         double sum = 0.0;
         float thr = KC > 0 ? fmaxf(kd[KS - 1], eps2) : eps2;
+        if (qpos >= n) thr = -INFINITY;     // pad lane of the last tile: nothing is in its reach
         float qn = 0.f;
 #pragma unroll
         for (int f = 0; f < D; ++f) qn = fmaf(q[f], q[f], qn);
@@ -358,6 +359,33 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
         cptr<float> sboxes = as_const((const float*)Jp->sboxes);
         cptr<float> hboxes = as_const((const float*)Jp->hboxes);
         const int halves = H ? Jp->halves : 0;
+        // H = 1: the next 64 super-tiles of a frontier are first tested at
+        // once, one per lane, with the query tile's box against each
+        // super-tile's box and the tile's largest threshold.  Per dimension
+        // that gap is at most each query's own gap (the same subtractions
+        // with the query replaced by its box's near corner, and float
+        // rounding is monotone), so a super-tile this drops is out of every
+        // query's reach; the ones it keeps get the per-query test.  Bit j of
+        // wmr is super-tile wbr + j, bit j of wml is super-tile wbl - j.
+        unsigned long long wmr = 0ull, wml = 0ull;
+        int wbr = -128, wbl = Jp->nsuper + 128;
+        auto super_window = [&](int s0, int dir) -> unsigned long long {
+            const int sj = s0 + dir * lane;
+            const float tmax = wave_max(thr);
+            bool ok = false;
+            if (sj >= 0 && sj < Jp->nsuper) {
+                const float* sb = (const float*)Jp->sboxes + (int64_t)sj * 2 * DP;
+                float lb = 0.f;
+#pragma unroll
+                for (int f = 0; f < D; ++f) {
+                    const float g = fmaxf(fmaxf(sb[f] - boxes[(int64_t)t0 * 2 * DP + DP + f],
+                                                boxes[(int64_t)t0 * 2 * DP + f] - sb[DP + f]), 0.f);
+                    lb = fmaf(g, g, lb);
+                }
+                ok = lb <= tmax;
+            }
+            return __ballot(ok);
+        };
         auto next_tile = [&]() -> int {
             if constexpr (H == 0) {
                 while (ws < nt) {
@@ -380,6 +408,20 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
                     if (rv && (!lv || wr - t0 <= t0 - wl)) {
                         if (prune && wr / kSuper != sr) {
                             sr = wr / kSuper;
+                            if (sr >= wbr + 64) {
+                                wbr = sr;
+                                wmr = super_window(sr, 1);
+                            }
+                            const unsigned long long rest = wmr >> (sr - wbr);
+                            if (!(rest & 1ull)) {
+                                // this super-tile and the next ones up to the
+                                // first the window keeps
+                                const int jump = rest ? __builtin_ctzll(rest) : 64 - (sr - wbr);
+                                const int e = min(nt, (sr + jump) * kSuper);
+                                skipped += e - wr;
+                                wr = e;
+                                continue;
+                            }
                             if (!reach_of(sboxes + (int64_t)sr * 2 * DP)) {
                                 const int e = min(nt, (sr + 1) * kSuper);
                                 skipped += e - wr;
@@ -391,6 +433,18 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
                     } else {
                         if (prune && wl / kSuper != sl) {
                             sl = wl / kSuper;
+                            if (sl <= wbl - 64) {
+                                wbl = sl;
+                                wml = super_window(sl, -1);
+                            }
+                            const unsigned long long rest = wml >> (wbl - sl);
+                            if (!(rest & 1ull)) {
+                                const int jump = rest ? __builtin_ctzll(rest) : 64 - (wbl - sl);
+                                const int e = max(-1, (sl - jump + 1) * kSuper - 1);
+                                skipped += wl - e;
+                                wl = e;
+                                continue;
+                            }
                             if (!reach_of(sboxes + (int64_t)sl * 2 * DP)) {
                                 skipped += wl - sl * kSuper + 1;
                                 wl = sl * kSuper - 1;
