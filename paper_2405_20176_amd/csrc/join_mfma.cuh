@@ -204,6 +204,31 @@ __device__ __forceinline__ h8v op(const u4v& w) {
     return __builtin_bit_cast(h8v, w);
 }
 
+// A kNN list entry as one 64-bit key: the float32 squared distance's bits
+// (non-negative, so their order is the distances' order) above the object
+// id, so that key order is (distance, id) order.  Empty slots hold the key
+// of (+inf, INT_MAX); the slots in front of the k real ones hold 0.
+typedef unsigned long long u64;
+constexpr u64 kEmptyKey = (0x7F800000ull << 32) | 0x7FFFFFFFull;
+__device__ __forceinline__ u64 knn_key(float dd, int id) {
+    return ((u64)__float_as_uint(dd) << 32) | (unsigned)id;
+}
+__device__ __forceinline__ float key_dist(u64 key) {
+    return __uint_as_float((unsigned)(key >> 32));
+}
+
+// Insert `key` into the ascending list kk of KC keys; the caller has checked
+// that it goes before the last one.
+template <int KC>
+__device__ __forceinline__ void key_insert(u64 (&kk)[KC], u64 key) {
+    bool b[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) b[j] = key < kk[j];
+#pragma unroll
+    for (int j = KC - 1; j > 0; --j) kk[j] = b[j - 1] ? kk[j - 1] : (b[j] ? key : kk[j]);
+    kk[0] = b[0] ? key : kk[0];
+}
+
 }  // namespace mfma_detail
 
 template <int D, int KC, int H>
@@ -254,17 +279,12 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
         float q[D];
 #pragma unroll
         for (int f = 0; f < D; ++f) q[f] = xs_g[(int64_t)qrow * DP + f];
-        float kd[KS];
-        int kid[KS];
+        u64 kk[KS];
 #pragma unroll
-        for (int j = 0; j < KS; ++j) {
-            const bool dummy = j < KS - k;
-            kd[j] = dummy ? -INFINITY : INFINITY;
-            kid[j] = dummy ? -1 : INT_MAX;
-        }
+        for (int j = 0; j < KS; ++j) kk[j] = j < KS - k ? 0ull : kEmptyKey;
         int cnt = 0;
         double sum = 0.0;
-        float thr = KC > 0 ? fmaxf(kd[KS - 1], eps2) : eps2;
+        float thr = KC > 0 ? fmaxf(key_dist(kk[KS - 1]), eps2) : eps2;
         if (qpos >= n) thr = -INFINITY;     // pad lane of the last tile: nothing is in its reach
         float qn = 0.f;
 #pragma unroll
@@ -325,8 +345,9 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
                 sum += (double)__builtin_amdgcn_sqrtf(dd);   // hardware sqrt, <= 1 ulp
             }
             if (KC > 0) {
-                if (before(dd, cid, kd[KS - 1], kid[KS - 1])) topk_insert<KS>(kd, kid, dd, cid);
-                const float nthr = fmaxf(kd[KS - 1], eps2);
+                const u64 key = knn_key(dd, cid);
+                if (key < kk[KS - 1]) key_insert<KS>(kk, key);
+                const float nthr = fmaxf(key_dist(kk[KS - 1]), eps2);
                 const bool moved = nthr != thr;
                 thr = nthr;
                 lim = f16_limit<D>(qn, thr);
@@ -626,18 +647,19 @@ __device__ __forceinline__ void join_mfma_body(JoinArgs A) {
 #pragma unroll
                 for (int j = 0; j < KS; ++j) {
                     if (j >= KS - k) {
-                        const float dj = sqrtf(kd[j]);
+                        const float dj = sqrtf(key_dist(kk[j]));
+                        const int kid = (int)(unsigned)kk[j];
                         accm += dj;
                         const int o = j - (KS - k);
-                        if (kids) kids[(int64_t)id * k + o] = kid[j];
+                        if (kids) kids[(int64_t)id * k + o] = kid;
                         if (kdist) kdist[(int64_t)id * k + o] = dj;
-                        if (indeg) atomicAdd(indeg + kid[j], 1);
+                        if (indeg) atomicAdd(indeg + kid, 1);
                     }
                 }
                 float* kmean = Jp->knn_mean;
                 if (kmean) kmean[id] = accm / (float)k;
                 float* kth = Jp->knn_kth;
-                if (kth) kth[id] = kd[KS - 1];
+                if (kth) kth[id] = key_dist(kk[KS - 1]);
             }
         }
     }
