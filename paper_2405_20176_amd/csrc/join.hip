@@ -16,7 +16,7 @@ int kc_class(int k) {
 size_t join_lds_bytes(int kc, int split) {
     if (split <= 1) return 0;   // also the matrix-core kernel (always one wavefront)
     const int ks = kc > 0 ? kc : 1;
-    // per wavefront and query slot: top-k distances and ids, eps counts, then
+    // per wavefront and query slot: top-k list keys, eps counts, then
     // the float64 eps sums (the offset of the last block is a multiple of 256)
     return (size_t)split * join_ql(kc) * (ks * 64 * 8 + 64 * 4 + 64 * 8);
 }

@@ -48,24 +48,29 @@ namespace snaps {
 
 namespace join_detail {
 
-__device__ __forceinline__ bool before(float d, int id, float bd, int bid) {
-    return d < bd || (d == bd && id < bid);
+// A kNN list entry as one 64-bit key: the float32 squared distance's bits
+// (non-negative, so their order is the distances' order) above the object
+// id, so that key order is (distance, id) order.  Empty slots hold the key
+// of (+inf, INT_MAX); the slots in front of the k real ones hold 0.
+typedef unsigned long long u64;
+constexpr u64 kEmptyKey = (0x7F800000ull << 32) | 0x7FFFFFFFull;
+__device__ __forceinline__ u64 knn_key(float dd, int id) {
+    return ((u64)__float_as_uint(dd) << 32) | (unsigned)id;
+}
+__device__ __forceinline__ float key_dist(u64 key) {
+    return __uint_as_float((unsigned)(key >> 32));
 }
 
-// Insert (dn, idn) into the ascending list (kd, kid) of KC slots; the caller
-// has checked that it goes before the last slot.
+// Insert `key` into the ascending list kk of KC keys; the caller has checked
+// that it goes before the last one.
 template <int KC>
-__device__ __forceinline__ void topk_insert(float (&kd)[KC], int (&kid)[KC], float dn, int idn) {
+__device__ __forceinline__ void key_insert(u64 (&kk)[KC], u64 key) {
     bool b[KC];
 #pragma unroll
-    for (int j = 0; j < KC; ++j) b[j] = before(dn, idn, kd[j], kid[j]);
+    for (int j = 0; j < KC; ++j) b[j] = key < kk[j];
 #pragma unroll
-    for (int j = KC - 1; j > 0; --j) {
-        kd[j] = b[j - 1] ? kd[j - 1] : (b[j] ? dn : kd[j]);
-        kid[j] = b[j - 1] ? kid[j - 1] : (b[j] ? idn : kid[j]);
-    }
-    kd[0] = b[0] ? dn : kd[0];
-    kid[0] = b[0] ? idn : kid[0];
+    for (int j = KC - 1; j > 0; --j) kk[j] = b[j - 1] ? kk[j - 1] : (b[j] ? key : kk[j]);
+    kk[0] = b[0] ? key : kk[0];
 }
 
 // Lower limit of the expanded-form score of a candidate that can still
@@ -150,7 +155,7 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
     constexpr int DP = row_stride(D);
     constexpr int KS = KC > 0 ? KC : 1;
     constexpr float cq = (float)(2 * (8 * D + 24)) * 5.9604644775390625e-8f;
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_unit, s_queue;
 
     const int S = A.split;
@@ -180,8 +185,7 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
 
         int qpos[QL];
         float q[QL][D];
-        float kd[QL][KS];
-        int kid[QL][KS];
+        u64 kk[QL][KS];
         int cnt[QL];
         double sum[QL];
         float thr[QL], qn[QL], lim[QL];
@@ -193,14 +197,10 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
 #pragma unroll
             for (int f = 0; f < D; ++f) q[r][f] = xs_g[(int64_t)qrow * DP + f];
 #pragma unroll
-            for (int j = 0; j < KS; ++j) {
-                const bool dummy = j < KS - k;     // slots in front of the k real ones
-                kd[r][j] = dummy ? -INFINITY : INFINITY;
-                kid[r][j] = dummy ? -1 : INT_MAX;
-            }
+            for (int j = 0; j < KS; ++j) kk[r][j] = j < KS - k ? 0ull : kEmptyKey;   // 0: slots in front of the k real ones
             cnt[r] = 0;
             sum[r] = 0.0;
-            thr[r] = KC > 0 ? fmaxf(kd[r][KS - 1], eps2) : eps2;
+            thr[r] = KC > 0 ? fmaxf(key_dist(kk[r][KS - 1]), eps2) : eps2;
             if (qpos[r] >= n) thr[r] = -INFINITY;             // no query (pad lane or missing tile): nothing in reach
             qn[r] = 0.f;
 #pragma unroll
@@ -219,8 +219,9 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
                 sum[r] += (double)__builtin_amdgcn_sqrtf(dd);   // hardware sqrt, <= 1 ulp
             }
             if (KC > 0) {
-                if (before(dd, cid, kd[r][KS - 1], kid[r][KS - 1])) topk_insert<KS>(kd[r], kid[r], dd, cid);
-                thr[r] = fmaxf(kd[r][KS - 1], eps2);
+                const u64 key = knn_key(dd, cid);
+                if (key < kk[r][KS - 1]) key_insert<KS>(kk[r], key);
+                thr[r] = fmaxf(key_dist(kk[r][KS - 1]), eps2);
                 if (XF) lim[r] = xf_limit(qn[r], thr[r], cq);
             }
         };
@@ -342,23 +343,18 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
         }
 
         // Merge the split wavefronts' partial results into wavefront 0.
-        // LDS layout per wavefront and query slot r: KS distances and KS ids
-        // (64 lanes each), the eps count, then (after all of those) the float64
-        // eps sums.
+        // LDS layout per wavefront and query slot r: KS list keys (64 lanes
+        // each), the eps count, then (after all of those) the float64 eps sums.
         if (S > 1) {
-            float* mkd = reinterpret_cast<float*>(smem);
-            int* mkid = reinterpret_cast<int*>(mkd + S * QL * KS * 64);
-            int* mcnt = mkid + S * QL * KS * 64;
+            u64* mkk = reinterpret_cast<u64*>(smem);
+            int* mcnt = reinterpret_cast<int*>(mkk + S * QL * KS * 64);
             double* msum = reinterpret_cast<double*>(smem + (size_t)S * QL * (KS * 64 * 8 + 64 * 4));
             if (wave > 0) {
 #pragma unroll
                 for (int r = 0; r < QL; ++r) {
                     const int wr = wave * QL + r;
 #pragma unroll
-                    for (int j = 0; j < KS; ++j) {
-                        mkd[(wr * KS + j) * 64 + lane] = kd[r][j];
-                        mkid[(wr * KS + j) * 64 + lane] = kid[r][j];
-                    }
+                    for (int j = 0; j < KS; ++j) mkk[(wr * KS + j) * 64 + lane] = kk[r][j];
                     mcnt[wr * 64 + lane] = cnt[r];
                     msum[wr * 64 + lane] = sum[r];
                 }
@@ -375,10 +371,8 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
 #pragma unroll
                             for (int j = 0; j < KS; ++j) {
                                 if (j >= KS - k) {
-                                    const float dn = mkd[(wr * KS + j) * 64 + lane];
-                                    const int idn = mkid[(wr * KS + j) * 64 + lane];
-                                    if (before(dn, idn, kd[r][KS - 1], kid[r][KS - 1]))
-                                        topk_insert<KS>(kd[r], kid[r], dn, idn);
+                                    const u64 key = mkk[(wr * KS + j) * 64 + lane];
+                                    if (key < kk[r][KS - 1]) key_insert<KS>(kk[r], key);
                                 }
                             }
                         }
@@ -406,18 +400,19 @@ __global__ __launch_bounds__(512) void k_join(JoinArgs A) {
 #pragma unroll
                     for (int j = 0; j < KS; ++j) {
                         if (j >= KS - k) {
-                            const float dj = sqrtf(kd[r][j]);
+                            const float dj = sqrtf(key_dist(kk[r][j]));
+                            const int kid = (int)(unsigned)kk[r][j];
                             accm += dj;
                             const int o = j - (KS - k);
-                            if (kids) kids[(int64_t)id * k + o] = kid[r][j];
+                            if (kids) kids[(int64_t)id * k + o] = kid;
                             if (kdist) kdist[(int64_t)id * k + o] = dj;
-                            if (indeg) atomicAdd(indeg + kid[r][j], 1);
+                            if (indeg) atomicAdd(indeg + kid, 1);
                         }
                     }
                     float* kmean = Jp->knn_mean;
                     if (kmean) kmean[id] = accm / (float)k;
                     float* kth = Jp->knn_kth;
-                    if (kth) kth[id] = kd[r][KS - 1];
+                    if (kth) kth[id] = key_dist(kk[r][KS - 1]);
                 }
             }
         }

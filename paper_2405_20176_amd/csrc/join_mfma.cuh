@@ -204,30 +204,6 @@ __device__ __forceinline__ h8v op(const u4v& w) {
     return __builtin_bit_cast(h8v, w);
 }
 
-// A kNN list entry as one 64-bit key: the float32 squared distance's bits
-// (non-negative, so their order is the distances' order) above the object
-// id, so that key order is (distance, id) order.  Empty slots hold the key
-// of (+inf, INT_MAX); the slots in front of the k real ones hold 0.
-typedef unsigned long long u64;
-constexpr u64 kEmptyKey = (0x7F800000ull << 32) | 0x7FFFFFFFull;
-__device__ __forceinline__ u64 knn_key(float dd, int id) {
-    return ((u64)__float_as_uint(dd) << 32) | (unsigned)id;
-}
-__device__ __forceinline__ float key_dist(u64 key) {
-    return __uint_as_float((unsigned)(key >> 32));
-}
-
-// Insert `key` into the ascending list kk of KC keys; the caller has checked
-// that it goes before the last one.
-template <int KC>
-__device__ __forceinline__ void key_insert(u64 (&kk)[KC], u64 key) {
-    bool b[KC];
-#pragma unroll
-    for (int j = 0; j < KC; ++j) b[j] = key < kk[j];
-#pragma unroll
-    for (int j = KC - 1; j > 0; --j) kk[j] = b[j - 1] ? kk[j - 1] : (b[j] ? key : kk[j]);
-    kk[0] = b[0] ? key : kk[0];
-}
 
 }  // namespace mfma_detail
 
