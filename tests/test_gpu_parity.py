@@ -167,7 +167,7 @@ def test_matrix_core_prefilter_every_d_and_k(S, d):
         check_scores(b, run_oracle(x, mask, k, eps), k, eps, label=f"matrix cores d={d} k={k}")
 
 
-@pytest.mark.parametrize("case", ["beyond_range", "some_beyond_range", "tiny_scale", "offset_negative"])
+@pytest.mark.parametrize("case", ["beyond_range", "some_beyond_range", "tiny_scale", "offset_negative", "edge_of_range"])
 @pytest.mark.parametrize("d", [3, 8, 15])
 def test_matrix_core_half_precision_range(S, case, d):
     """The matrix cores screen with half-precision pieces of coordinates up to
@@ -176,7 +176,8 @@ def test_matrix_core_half_precision_range(S, case, d):
     coordinates near the half-precision subnormal range and populations far
     from the origin keep a valid limit.  Outputs equal the direct form's bit
     for bit and meet the oracle."""
-    rng = np.random.default_rng(["beyond_range", "some_beyond_range", "tiny_scale", "offset_negative"].index(case) * 31 + d)
+    rng = np.random.default_rng(["beyond_range", "some_beyond_range", "tiny_scale", "offset_negative",
+                                 "edge_of_range"].index(case) * 31 + d)
     n = 3000
     x = rng.random((n, 16)).astype(np.float32)
     if case == "beyond_range":
@@ -185,6 +186,12 @@ def test_matrix_core_half_precision_range(S, case, d):
         x[rng.choice(n, 5, replace=False)] *= np.float32(100.0)
     elif case == "tiny_scale":
         x = (x * 3e-6).astype(np.float32)
+    elif case == "edge_of_range":
+        # exactly +-32 is in range, the next float above 32 is not
+        x = ((x - 0.5) * 64.0).astype(np.float32)
+        x[rng.choice(n, 20, replace=False), rng.integers(0, 16, 20)] = np.float32(32.0)
+        x[rng.choice(n, 20, replace=False), rng.integers(0, 16, 20)] = np.float32(-32.0)
+        x[rng.choice(n, 3, replace=False), 0] = np.nextafter(np.float32(32.0), np.float32(64.0))
     else:
         x = (x * 0.5 - 31.0).astype(np.float32)
     mask = (1 << d) - 1
