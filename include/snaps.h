@@ -123,7 +123,10 @@ typedef struct {
 typedef struct {
     int32_t mode;           /* 0 auto (2 up to d = 14, else 1), 1 brute force over every candidate
                                tile, 2 skip candidate tiles whose bounding box is provably out of reach */
-    int32_t split;          /* 0 auto, else waves sharing one query tile: 1, 2, 4 or 8 */
+    int32_t split;          /* 0 auto (1, the matrix-core kernel, when it applies and the call
+                               has at least 48 query tiles; else enough wavefronts per SIMD
+                               for the vector-ALU kernel), else waves sharing one query
+                               tile: 1, 2, 4 or 8 */
     int32_t index_dims;     /* 0 auto (min(d, 4): the autotuner's usual choice; Sec. 3.8.1 uses
                                min(d, 6), which serving states keep), else 1..min(d, 6) */
     int32_t filter;         /* 0 auto (3), 1 direct distance form only,

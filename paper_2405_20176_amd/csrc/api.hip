@@ -323,10 +323,18 @@ DevJob make_devjob(const snaps_population* P, uint32_t mask, const JobPlan& p, f
 
 constexpr size_t kMaxJoinLds = 120 * 1024;
 
-int choose_split(const Tune& tn, int64_t total_units, int cus, int kc) {
+// Query tiles from which the matrix-core kernel (one wavefront per tile)
+// beats the split vector-ALU kernel even with SIMDs left idle (measured on
+// MI355X over single jobs of 500 to 31,693 objects, d = 2..15: about equal at
+// 32 tiles, 7-12 % faster at 63, 25-45 % at 250 and more).
+constexpr int64_t kMfmaMinUnits = 48;
+
+int choose_split(const Tune& tn, int64_t total_units, int cus, int kc, bool mfma) {
     int s = 1;
     if (tn.split > 0) {
         s = tn.split;
+    } else if (mfma && total_units >= kMfmaMinUnits) {
+        s = 1;
     } else {
         // Aim for about eight wavefronts per SIMD (four SIMDs per CU).
         const int64_t target = (int64_t)cus * 4 * 8;
@@ -373,7 +381,7 @@ int launch_joins(const Meta& meta, const std::vector<ClassPlan>& plans, const Tu
         const int d = class_d(c);
         const int kc = class_kc(c);
         const int hier = class_hier(c);
-        const int split = mq > 1 ? 1 : choose_split(tn, all_units, cus, kc);
+        const int split = mq > 1 ? 1 : choose_split(tn, all_units, cus, kc, xf_pref == 2);
         // the matrix-core kernel runs one wavefront per query tile
         const int xf = (xf_pref == 2 && (split > 1 || mq > 1)) ? 1 : xf_pref;
         JoinArgs a{};
