@@ -321,7 +321,8 @@ typedef struct {
     const float* alerts;    /* [m][d] row-major, the subspace's columns in ascending
                                feature order, normalised with the population's bounds */
     int32_t m;              /* number of alerts (0 allowed) */
-    int32_t pad0;
+    int32_t method;         /* 0 automatic, 1 one wavefront per alert, 2 matrix-core
+                               cross-join of 64-alert groups (see snaps_alerts_score) */
     int32_t* eps_count;     /* [m] outputs */
     float* eps_mean;
     int32_t* indeg;
@@ -331,14 +332,36 @@ typedef struct {
 
 /* Score n_jobs alert batches whose states all have dimensionality d and the
  * same k (the job list is host memory, read during the call).  Jobs may use
- * different states and populations.  One wavefront scores one alert; the
- * results of an alert do not depend on the other alerts or jobs of the call.
+ * different states and populations.  Two kernels compute the same scores:
+ *   method 1: one wavefront per alert walks the population's index;
+ *   method 2: a cross-join of groups of 64 alerts against the population's
+ *             tiles, screened on the matrix cores (the half-precision
+ *             contraction of the join, widened so that a pair passes if the
+ *             alert may list the object or the object may count the alert)
+ *             with every passing pair re-evaluated exactly; the population
+ *             is cut into slices whose partial results are merged in a
+ *             fixed order;
+ *   method 0: 2 for d >= 7, else 1.
+ * Both give identical eps counts, in-degrees, kNN means and their rank
+ * positions; the eps mean (a float64 sum taken in another order) may differ
+ * in the last float bit.  A job's kernel and slicing depend only on its own
+ * method, d and m, so the results of an alert do not depend on the other
+ * alerts or jobs of the call.
+ *   ws   device workspace of snaps_alerts_workspace_bytes(jobs, n_jobs, d, k)
+ *        bytes (0, and NULL allowed, when no job runs method 2); it must not
+ *        be used by anything else until the call's work on stream is done.
  * The state header lives in device memory, so a mismatch is found on the
  * device: an alert whose state has another dimensionality than d, or a k
  * above the top-k capacity chosen for k, is not scored (eps_count and indeg
  * are set to -1, the means to NaN, ranks are left untouched).  At most 2^31
  * alerts per call.  Asynchronous on stream. */
-int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k, void* stream);
+int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes snaps_alerts_score needs for these jobs: the partial
+ * results of the method-2 jobs' slices; 0 for invalid arguments or when no
+ * job runs method 2.  Pure host function. */
+size_t snaps_alerts_workspace_bytes(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k);
 
 /* ------------------------------------------------------------------------
  * Sampled-distance search radius (paper Sec. 3.5.3).  The paper picks the

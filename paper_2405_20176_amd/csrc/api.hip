@@ -1144,6 +1144,21 @@ struct ServeLayout {
     int nsuper;
 };
 
+// Kernel of one alert job: 1 = one wavefront per alert (k_alerts), 2 = the
+// matrix-core cross-join of 64-alert groups (k_alerts_mfma).  Automatic
+// choice: the matrix cores from kAlertMfmaMinD dimensions, where the
+// per-alert walk meets most tiles (measured on 10^6-object states with
+// 16..10^4 alerts per request: at d = 7 the matrix cores are 1.3-3.5x
+// faster, at d = 15 10-18x; at d = 6 faster only below ~500 alerts, at
+// d <= 5 slower, the per-alert index culling there being the better tool).
+constexpr int kAlertMfmaMinD = 7;
+
+int alert_method(int method, int d, int m) {
+    (void)m;
+    if (method != 0) return method;
+    return d >= kAlertMfmaMinD ? 2 : 1;
+}
+
 ServeLayout serve_layout(int64_t n, int d, int k) {
     ServeLayout L{};
     L.plan = plan_job(n, d, k, true, kIndexRadix, true);
@@ -1275,7 +1290,21 @@ int snaps_serve_state_outputs(const void* state, int64_t n, int32_t d, int32_t k
     return SNAPS_OK;
 }
 
-int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k, void* stream) {
+size_t snaps_alerts_workspace_bytes(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k) {
+    if (n_jobs < 1 || !jobs || d < 2 || d > kMaxD || k < 1 || k > kMaxK) return 0;
+    const int kc = kc_class(k);
+    size_t bytes = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const snaps_alert_job& a = jobs[i];
+        if (a.m <= 0 || alert_method(a.method, d, a.m) != 2) continue;
+        const int64_t groups = (a.m + kTile - 1) / kTile;
+        bytes += align_up((size_t)(groups * alert_slices(a.m) * alert_part_floats(kc)) * sizeof(float));
+    }
+    return bytes;
+}
+
+int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k, void* ws, size_t ws_bytes,
+                       void* stream) {
     if (n_jobs < 1 || !jobs) return fail(SNAPS_EINVAL, "need at least one alert job");
     if (d < 2 || d > kMaxD) return fail(SNAPS_EINVAL, "d must be in [2, %d]", kMaxD);
     if (k < 1 || k > kMaxK) return fail(SNAPS_EINVAL, "k must be in [1, %d]", kMaxK);
@@ -1285,32 +1314,60 @@ int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, i
         if (!a.state || (a.m > 0 && (!a.alerts || !a.eps_count || !a.eps_mean || !a.indeg || !a.knn_mean)))
             return fail(SNAPS_EINVAL, "alert job %d: state, alerts and every score output are required", i);
         if (a.m < 0) return fail(SNAPS_EINVAL, "alert job %d: negative alert count", i);
+        if (a.method < 0 || a.method > 2) return fail(SNAPS_EINVAL, "alert job %d: method must be 0, 1 or 2", i);
     }
+    const size_t need = snaps_alerts_workspace_bytes(jobs, n_jobs, d, k);
+    if (need > 0 && !ws) return fail(SNAPS_EINVAL, "workspace is NULL (%zu bytes needed)", need);
+    if (ws_bytes < need) return fail(SNAPS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
     const int kc = kc_class(k);
-    for (int b = 0; b < n_jobs; b += kAlertJobs) {
-        AlertArgs aa{};
-        int64_t alerts = 0;
-        const int nb = std::min(kAlertJobs, n_jobs - b);
-        aa.n_jobs = nb;
-        for (int i = 0; i < nb; ++i) {
-            const snaps_alert_job& a = jobs[b + i];
-            AlertJob& J = aa.jobs[i];
-            J.st = static_cast<const ServeState*>(a.state);
-            J.alerts = a.alerts;
-            J.m = a.m;
-            J.eps_count = a.eps_count;
-            J.eps_mean = a.eps_mean;
-            J.indeg = a.indeg;
-            J.knn_mean = a.knn_mean;
-            J.rank = a.rank;
-            aa.alert_prefix[i] = (int32_t)alerts;
-            alerts += a.m;
-            if (alerts > INT32_MAX - kAlertWaves)
-                return fail(SNAPS_EINVAL, "more than 2^31 alerts in one call");
+    // Each job's kernel and slice count depend only on its own method, d and
+    // size, so an alert's scores do not depend on the other jobs of the call.
+    size_t part_at = 0;                          // floats into ws
+    for (int mfma = 0; mfma < 2; ++mfma) {
+        std::vector<int> sel;
+        for (int i = 0; i < n_jobs; ++i)
+            if (jobs[i].m > 0 && alert_method(jobs[i].method, d, jobs[i].m) == (mfma ? 2 : 1)) sel.push_back(i);
+        for (size_t b = 0; b < sel.size(); b += kAlertJobs) {
+            AlertArgs aa{};
+            int64_t alerts = 0, blocks = 0, groups = 0;
+            const int nb = (int)std::min<size_t>(kAlertJobs, sel.size() - b);
+            aa.n_jobs = nb;
+            aa.d = d;
+            aa.part = static_cast<float*>(ws);
+            for (int i = 0; i < nb; ++i) {
+                const snaps_alert_job& a = jobs[sel[b + i]];
+                AlertJob& J = aa.jobs[i];
+                J.st = static_cast<const ServeState*>(a.state);
+                J.alerts = a.alerts;
+                J.m = a.m;
+                J.eps_count = a.eps_count;
+                J.eps_mean = a.eps_mean;
+                J.indeg = a.indeg;
+                J.knn_mean = a.knn_mean;
+                J.rank = a.rank;
+                aa.alert_prefix[i] = (int32_t)alerts;
+                aa.group_prefix[i] = (int32_t)blocks;
+                aa.merge_prefix[i] = (int32_t)groups;
+                alerts += a.m;
+                if (alerts > INT32_MAX - kAlertWaves)
+                    return fail(SNAPS_EINVAL, "more than 2^31 alerts in one call");
+                if (mfma) {
+                    const int64_t g = (a.m + kTile - 1) / kTile;
+                    const int sl = alert_slices(a.m);
+                    aa.slices[i] = sl;
+                    aa.part_off[i] = (int64_t)part_at;
+                    part_at += align_up((size_t)(g * sl * alert_part_floats(kc)) * sizeof(float)) / sizeof(float);
+                    blocks += g * sl;
+                    groups += g;
+                    if (blocks > INT32_MAX) return fail(SNAPS_EINVAL, "too many alert groups in one call");
+                }
+            }
+            aa.alert_prefix[nb] = (int32_t)alerts;
+            aa.group_prefix[nb] = (int32_t)blocks;
+            aa.merge_prefix[nb] = (int32_t)groups;
+            hipError_t e = mfma ? launch_alerts_mfma(d, kc, aa, s) : launch_alerts(d, kc, aa, s);
+            if (e != hipSuccess) return hip_fail(e, "alert scoring launch");
         }
-        aa.alert_prefix[nb] = (int32_t)alerts;
-        hipError_t e = launch_alerts(d, kc, aa, s);
-        if (e != hipSuccess) return hip_fail(e, "alert scoring launch");
     }
     return SNAPS_OK;
 }

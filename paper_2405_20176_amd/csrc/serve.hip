@@ -26,6 +26,8 @@
 #include "common.cuh"
 #include "keys.cuh"
 #include "join_kernel.cuh"
+#include "serve.cuh"
+#include "serve_mfma.cuh"
 
 #include <climits>
 
@@ -79,29 +81,6 @@ hipError_t launch_serve_super(int ntiles, int dp, const float* boxes, const floa
     return hipGetLastError();
 }
 
-namespace alert_detail {
-
-// Squared float32 distance from q to the box [lo, hi] (0 inside), computed
-// with the same operations in the same order as a point distance, so it
-// never exceeds the float32 distance of any point in the box.
-template <int D, int DP>
-__device__ __forceinline__ float box_dist2(const float (&q)[D], const float* b) {
-    float lb = 0.f;
-#pragma unroll
-    for (int f = 0; f < D; ++f) {
-        const float g = fmaxf(fmaxf(b[f] - q[f], q[f] - b[DP + f]), 0.f);
-        lb = fmaf(g, g, lb);
-    }
-    return lb;
-}
-
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-}  // namespace alert_detail
 
 template <int D, int KC>
 __global__ __launch_bounds__(64 * kAlertWaves) void k_alerts(AlertArgs A) {
@@ -280,13 +259,7 @@ __global__ __launch_bounds__(64 * kAlertWaves) void k_alerts(AlertArgs A) {
                              : mtr == 1 ? ~asc_key(cnt > 0 ? mean : INFINITY)
                              : mtr == 2 ? (uint32_t)deg
                                         : ~asc_key(kmean);
-        const uint32_t* dv = St->distinct[mtr];
-        int a = 0, b = St->n_distinct[mtr];
-        while (a < b) {
-            const int mid = (a + b) >> 1;
-            if (dv[mid] < key_m) a = mid + 1; else b = mid;
-        }
-        J.rank[(int64_t)mtr * J.m + ai] = a;
+        J.rank[(int64_t)mtr * J.m + ai] = distinct_below(St->distinct[mtr], St->n_distinct[mtr], key_m);
     }
 }
 
@@ -337,6 +310,98 @@ hipError_t launch_alerts(int D, int kc, const AlertArgs& a, hipStream_t s) {
     void* args[] = {&copy};
     const int grid = (total + kAlertWaves - 1) / kAlertWaves;
     return hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(64 * kAlertWaves), args, 0, s);
+}
+
+// Merges the slices' partial results of one group of 64 alerts (one lane
+// per alert), in slice order, and writes the scores and rank positions
+// exactly as k_alerts does: the k nearest distances are the k smallest of
+// the slices' lists, and the kNN mean is lane 0's result of k_alerts'
+// wavefront sum (each lane i of the first 32 holding slot i, the others 0),
+// step by step.
+template <int KC>
+__global__ __launch_bounds__(64) void k_alerts_merge(AlertArgs A) {
+    using namespace alert_detail;
+    constexpr int KS = KC;
+    static_assert(KS <= 32, "the kNN mean's reduction order assumes at most 32 slots");
+    const int lane = threadIdx.x;
+    const int g = blockIdx.x;
+    if (g >= A.merge_prefix[A.n_jobs]) return;
+    int lo = 0, hi = A.n_jobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (A.merge_prefix[mid] <= g) lo = mid; else hi = mid;
+    }
+    const AlertJob& J = A.jobs[lo];
+    const int gi = g - A.merge_prefix[lo];
+    const int ai = gi * kTile + lane;
+    if (ai >= J.m) return;
+    const ServeState* St = J.st;
+    const int k = St->k;
+    if (St->d != A.d || k < 1 || k > KS) {       // state of another shape: flag the alert
+        J.eps_count[ai] = -1;
+        J.indeg[ai] = -1;
+        J.eps_mean[ai] = NAN;
+        J.knn_mean[ai] = NAN;
+        return;
+    }
+    const int nsl = A.slices[lo];
+    const float* part = A.part + A.part_off[lo] + (int64_t)gi * nsl * alert_part_floats(KS);
+    float kd[KS];
+#pragma unroll
+    for (int j = 0; j < KS; ++j) kd[j] = j < KS - k ? -INFINITY : INFINITY;
+    int cnt = 0, deg = 0;
+    double sum = 0.0;
+    for (int s = 0; s < nsl; ++s) {
+        const float* ps = part + (int64_t)s * alert_part_floats(KS);
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            if (j >= KS - k) {
+                const float v = ps[j * kTile + lane];
+                if (v < kd[KS - 1]) alert_mfma_detail::dist_insert<KS>(kd, v);
+            }
+        }
+        cnt += __float_as_int(ps[KS * kTile + lane]);
+        deg += __float_as_int(ps[(KS + 1) * kTile + lane]);
+        const unsigned long long lo32 = (unsigned)__float_as_int(ps[(KS + 2) * kTile + lane]);
+        const unsigned long long hi32 = (unsigned)__float_as_int(ps[(KS + 3) * kTile + lane]);
+        sum += __longlong_as_double((long long)((hi32 << 32) | lo32));
+    }
+    float v[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = (i >= KS - k && i < KS) ? __builtin_amdgcn_sqrtf(kd[i]) : 0.f;
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+#pragma unroll
+        for (int i = 0; i < o; ++i) v[i] += v[i + o];
+    }
+    const float kmean = v[0] / (float)k;
+    const float mean = cnt > 0 ? (float)(sum / (double)cnt) : 0.f;
+    J.eps_count[ai] = cnt;
+    J.eps_mean[ai] = mean;
+    J.indeg[ai] = deg;
+    J.knn_mean[ai] = kmean;
+    if (J.rank) {
+        J.rank[ai] = distinct_below(St->distinct[0], St->n_distinct[0], (uint32_t)cnt);
+        J.rank[(int64_t)J.m + ai] =
+            distinct_below(St->distinct[1], St->n_distinct[1], ~asc_key(cnt > 0 ? mean : INFINITY));
+        J.rank[(int64_t)2 * J.m + ai] = distinct_below(St->distinct[2], St->n_distinct[2], (uint32_t)deg);
+        J.rank[(int64_t)3 * J.m + ai] = distinct_below(St->distinct[3], St->n_distinct[3], ~asc_key(kmean));
+    }
+}
+
+hipError_t launch_alerts_mfma(int D, int kc, const AlertArgs& a, hipStream_t s) {
+    AlertKernel fn = D <= 8 ? alert_mfma_pick_group0(D, kc) : alert_mfma_pick_group1(D, kc);
+    AlertKernel mfn = kc == 5 ? k_alerts_merge<5> : kc == 10 ? k_alerts_merge<10> : kc == 20 ? k_alerts_merge<20>
+                    : kc == 32 ? k_alerts_merge<32> : nullptr;
+    if (!fn || !mfn) return hipErrorInvalidValue;
+    const int blocks = a.group_prefix[a.n_jobs];
+    if (blocks <= 0) return hipSuccess;
+    AlertArgs copy = a;
+    void* args[] = {&copy};
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(blocks), dim3(64 * kAlertMfmaWaves),
+                                   args, 0, s);
+    if (e != hipSuccess) return e;
+    return hipLaunchKernel(reinterpret_cast<const void*>(mfn), dim3(a.merge_prefix[a.n_jobs]), dim3(64), args, 0, s);
 }
 
 }  // namespace snaps

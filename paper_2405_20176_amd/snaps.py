@@ -63,7 +63,7 @@ PASS_INDEX, PASS_JOIN, PASS_RANK = 1, 2, 4
 
 class c_alert_job(ctypes.Structure):
     _fields_ = [("state", ctypes.c_void_p), ("alerts", ctypes.c_void_p), ("m", ctypes.c_int32),
-                ("pad0", ctypes.c_int32), ("eps_count", ctypes.c_void_p), ("eps_mean", ctypes.c_void_p),
+                ("method", ctypes.c_int32), ("eps_count", ctypes.c_void_p), ("eps_mean", ctypes.c_void_p),
                 ("indeg", ctypes.c_void_p), ("knn_mean", ctypes.c_void_p), ("rank", ctypes.c_void_p)]
 
 
@@ -134,7 +134,9 @@ def load_library(path: str = LIB_PATH):
     lib.snaps_serve_state_outputs.restype = ctypes.c_int
     lib.snaps_serve_state_outputs.argtypes = [vp, i64, i32, i32, P(vp), P(vp), P(vp), P(vp), P(vp)]
     lib.snaps_alerts_score.restype = ctypes.c_int
-    lib.snaps_alerts_score.argtypes = [P(c_alert_job), i32, i32, i32, vp]
+    lib.snaps_alerts_score.argtypes = [P(c_alert_job), i32, i32, i32, vp, sz, vp]
+    lib.snaps_alerts_workspace_bytes.restype = sz
+    lib.snaps_alerts_workspace_bytes.argtypes = [P(c_alert_job), i32, i32, i32]
     lib.snaps_eps_sample_workspace.restype = sz
     lib.snaps_eps_sample_workspace.argtypes = [P(c_eps_job), i32]
     lib.snaps_eps_sample.restype = ctypes.c_int
@@ -558,19 +560,21 @@ class AlertJob:
     indeg: torch.Tensor
     knn_mean: torch.Tensor
     rank: Optional[torch.Tensor] = None
+    method: int = 0          # 0 automatic, 1 one wavefront per alert, 2 matrix-core tiles of 64 alerts
 
     @classmethod
-    def alloc(cls, state: ServeState, alerts: torch.Tensor, with_rank: bool = True) -> "AlertJob":
+    def alloc(cls, state: ServeState, alerts: torch.Tensor, with_rank: bool = True, method: int = 0) -> "AlertJob":
         m = alerts.shape[0]
         dev = alerts.device
         return cls(state, alerts, torch.empty(m, dtype=torch.int32, device=dev),
                    torch.empty(m, dtype=torch.float32, device=dev), torch.empty(m, dtype=torch.int32, device=dev),
                    torch.empty(m, dtype=torch.float32, device=dev),
-                   torch.empty((4, m), dtype=torch.int32, device=dev) if with_rank else None)
+                   torch.empty((4, m), dtype=torch.int32, device=dev) if with_rank else None, method)
 
 
 def snaps_alerts_score(jobs: Sequence[AlertJob], stream=None):
-    """Score alert batches; jobs are grouped by (d, k) into library calls."""
+    """Score alert batches; jobs are grouped by (d, k) into library calls,
+    each with the workspace it needs (allocated on the calling stream)."""
     lib = load_library()
     groups = {}
     for j in jobs:
@@ -588,7 +592,10 @@ def snaps_alerts_score(jobs: Sequence[AlertJob], stream=None):
             arr[i].indeg = j.indeg.data_ptr()
             arr[i].knn_mean = j.knn_mean.data_ptr()
             arr[i].rank = None if j.rank is None else j.rank.data_ptr()
-        _check(lib.snaps_alerts_score(arr, len(js), d, k, _stream(stream)))
+            arr[i].method = int(j.method)
+        need = lib.snaps_alerts_workspace_bytes(arr, len(js), d, k)
+        ws = _workspace(need, js[0].alerts.device) if need else None
+        _check(lib.snaps_alerts_score(arr, len(js), d, k, _ptr(ws), need, _stream(stream)))
 
 
 def snaps_eps_sample(specs, stream=None):
@@ -615,6 +622,7 @@ def snaps_eps_sample(specs, stream=None):
     need = lib.snaps_eps_sample_workspace(arr, len(specs))
     if need == 0:
         _check(lib.snaps_eps_sample(arr, len(specs), None, 0, _stream(stream)))
+        return outs
     ws = _workspace(need, outs[0].device)
     _check(lib.snaps_eps_sample(arr, len(specs), _ptr(ws), ws.numel(), _stream(stream)))
     return outs

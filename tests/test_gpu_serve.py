@@ -30,9 +30,9 @@ def S():
     return snaps
 
 
-def score(S, state, alerts_np):
+def score(S, state, alerts_np, method=0):
     a = torch.from_numpy(np.ascontiguousarray(alerts_np, dtype=np.float32)).cuda()
-    job = S.AlertJob.alloc(state, a)
+    job = S.AlertJob.alloc(state, a, method=method)
     S.snaps_alerts_score([job])
     torch.cuda.synchronize()
     return {k: getattr(job, k).cpu().numpy() for k in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank")}
@@ -65,8 +65,11 @@ def _population_keys(po):
     return [cnt.astype(np.float64), -np.where(cnt > 0, mean, np.inf), deg.astype(np.float64), -km]
 
 
+@pytest.mark.parametrize("method", [1, 2])
 @pytest.mark.parametrize("n,d,k", [(3000, 3, 10), (20000, 2, 5), (40000, 7, 10), (12000, 13, 20)])
-def test_alerts_against_oracle(S, n, d, k):
+def test_alerts_against_oracle(S, n, d, k, method):
+    """Both kernels (1: one wavefront per alert, 2: matrix-core tiles of 64
+    alerts) against the oracle."""
     rng = np.random.default_rng(n + d)
     job = G.gen_c3_jobs(4)[2]
     x = G.gen_c3_population(job, n=n)
@@ -81,7 +84,7 @@ def test_alerts_against_oracle(S, n, d, k):
     A = O.project(alerts_full, mask).astype(np.float32)
     pop = S.Population.from_rows(x)
     st = S.ServeState(pop, mask, k, eps)
-    out = score(S, st, A)
+    out = score(S, st, A, method)
     # the population's exact k-th neighbour distances from the oracle's C
     # twin (float64 brute force, identical to the NumPy oracle)
     P32 = P.astype(np.float32)
@@ -169,10 +172,25 @@ def test_state_of_another_shape_is_flagged_not_read(S):
     arr[0].knn_mean = job.knn_mean.data_ptr()
     arr[0].rank = None
     lib = S.load_library()
-    assert lib.snaps_alerts_score(arr, 1, 4, 5, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)) == 0
-    torch.cuda.synchronize()
-    assert (job.eps_count.cpu().numpy() == -1).all() and (job.indeg.cpu().numpy() == -1).all()
-    assert torch.isnan(job.knn_mean).all() and torch.isnan(job.eps_mean).all()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for method in (1, 2):
+        job.eps_count.zero_()
+        job.indeg.zero_()
+        job.knn_mean.zero_()
+        job.eps_mean.zero_()
+        arr[0].method = method
+        need = lib.snaps_alerts_workspace_bytes(arr, 1, 4, 5)
+        assert (need > 0) == (method == 2)
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+        if need:                                       # a workspace too small, or none, is refused
+            assert lib.snaps_alerts_score(arr, 1, 4, 5, ctypes.c_void_p(ws.data_ptr()), need - 1, stream) != 0
+            assert lib.snaps_alerts_score(arr, 1, 4, 5, None, 0, stream) != 0
+        assert lib.snaps_alerts_score(arr, 1, 4, 5, ctypes.c_void_p(ws.data_ptr()), need, stream) == 0
+        torch.cuda.synchronize()
+        assert (job.eps_count.cpu().numpy() == -1).all() and (job.indeg.cpu().numpy() == -1).all(), method
+        assert torch.isnan(job.knn_mean).all() and torch.isnan(job.eps_mean).all(), method
+    arr[0].method = 3
+    assert lib.snaps_alerts_score(arr, 1, 3, 5, None, 0, stream) != 0
     # the same job with the right d is scored
     S.snaps_alerts_score([job])
     torch.cuda.synchronize()
@@ -253,3 +271,116 @@ def test_continuous_batching_mix_vs_alone(S):
                                           err_msg=f"request {r.rid} {key}")
         mixed_sizes |= r.m > 1000
     assert mixed_sizes
+
+
+def _both(S, st, a_np, with_rank=True):
+    a = torch.from_numpy(np.ascontiguousarray(a_np, dtype=np.float32)).cuda()
+    outs = []
+    for method in (1, 2):
+        j = S.AlertJob.alloc(st, a, with_rank=with_rank, method=method)
+        S.snaps_alerts_score([j])
+        outs.append(j)
+    torch.cuda.synchronize()
+    return [{k: getattr(j, k).cpu().numpy() for k in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank")
+             if getattr(j, k) is not None} for j in outs]
+
+
+def _assert_kernels_agree(w, t):
+    """The matrix-core kernel against the per-alert kernel: in-degree, eps
+    count and kNN mean (and their rank positions) identical; the eps mean,
+    whose float64 sum runs in another order, within one float32 ulp, its
+    rank position identical wherever the two means are."""
+    for key in ("eps_count", "indeg", "knn_mean"):
+        np.testing.assert_array_equal(t[key], w[key], err_msg=key)
+    diff = np.abs(t["eps_mean"].astype(np.float64) - w["eps_mean"].astype(np.float64))
+    assert (diff <= np.spacing(np.abs(w["eps_mean"])).astype(np.float64)).all()
+    if "rank" in w:
+        for r in (0, 2, 3):
+            np.testing.assert_array_equal(t["rank"][r], w["rank"][r], err_msg=f"rank {r}")
+        same = t["eps_mean"] == w["eps_mean"]
+        np.testing.assert_array_equal(t["rank"][1][same], w["rank"][1][same])
+
+
+@pytest.mark.parametrize("n,d,k,m", [(5000, 2, 5, 1), (20000, 6, 10, 63), (20000, 9, 20, 65), (70000, 12, 32, 700),
+                                     (30000, 15, 10, 130), (8000, 16, 5, 64), (3000, 7, 10, 1000),
+                                     (150000, 10, 10, 200)])
+def test_matrix_core_alerts_match_wavefront(S, n, d, k, m):
+    """Ragged alert counts (one alert, 63, 64, 65 ...), every k class, d from
+    2 to 16, populations from one to 37 super-tiles: alerts inside the bulk,
+    exact copies of population objects (distance 0), far outside, and on the
+    edge of the bulk."""
+    rng = np.random.default_rng(n + 31 * d + m)
+    job = G.gen_c3_jobs(4)[3]
+    x = G.gen_c3_population(job, n=n)
+    mask = int(sum(1 << f for f in rng.choice(15, size=min(d, 15), replace=False))) if d <= 15 else None
+    if mask is None:                                      # d = 16: one extra column
+        x = np.concatenate([x, rng.random((n, 1)).astype(np.float32)], axis=1)
+        mask = (1 << 16) - 1
+    P = O.project(x, mask).astype(np.float32)
+    eps = float(O.eps_sampled_mean_count(P.astype(np.float64), 10, 64, seed=d))
+    rows = rng.choice(n, size=m, replace=m > n)
+    a = P[rows] + rng.normal(0, 0.01, size=(m, d)).astype(np.float32)
+    a[: m // 4] = P[rows[: m // 4]]                       # exact copies
+    if m > 8:
+        a[-3:] = rng.uniform(-0.5, 1.5, size=(3, d)).astype(np.float32)
+        a[-1] = 5.0
+    pop = S.Population.from_rows(x)
+    st = S.ServeState(pop, mask, k, eps)
+    w, t = _both(S, st, a)
+    _assert_kernels_agree(w, t)
+    assert (w["indeg"] >= 0).all() and np.isfinite(w["knn_mean"]).all()
+
+
+@pytest.mark.parametrize("case", ["far_alerts", "large_population"])
+def test_matrix_core_alerts_out_of_half_range(S, case):
+    """Coordinates beyond the half-precision pieces' range (|x| > 32): a group
+    holding such an alert, or a tile holding such an object, is not screened
+    and every pair is re-evaluated; the scores stay those of the per-alert
+    kernel, and the oracle's in-degree and kNN mean."""
+    rng = np.random.default_rng(77)
+    n, d, k = 6000, 8, 10
+    x = rng.random((n, d)).astype(np.float32)
+    a = x[rng.choice(n, size=150, replace=False)] + rng.normal(0, 0.02, size=(150, d)).astype(np.float32)
+    if case == "far_alerts":
+        a[5] = 40.0
+        a[100, 3] = -1000.0
+    else:
+        x = x * 80.0 - 20.0                                # most objects beyond |x| = 32
+        a = a * 80.0 - 20.0
+    a = a.astype(np.float32)
+    pop = S.Population.from_rows(x)
+    eps = 0.3 if case == "far_alerts" else 20.0
+    st = S.ServeState(pop, (1 << d) - 1, k, eps)
+    w, t = _both(S, st, a)
+    _assert_kernels_agree(w, t)
+    popref = C.outlier_scores(x, k, eps)
+    ref = O.alert_scores(x, a, k, eps, pop=popref)
+    np.testing.assert_allclose(t["knn_mean"], ref["knn_mean"], rtol=TAU)
+    D = O.pair_distances(a, x)
+    rk = popref["knn_dist"][:, k - 1]
+    deg_ex = (np.abs(D - rk[None, :]) <= TAU * rk[None, :]).sum(axis=1)
+    assert (np.abs(t["indeg"] - ref["indeg"]) <= deg_ex).all()
+
+
+def test_mixed_methods_in_one_call(S):
+    """Jobs of both kernels and of states with different populations in one
+    call: every job's scores equal those of the same job scored alone."""
+    rng = np.random.default_rng(29)
+    pops = [S.Population.from_rows(rng.random((n, 15)).astype(np.float32)) for n in (7000, 11000)]
+    states = [S.ServeState(pops[0], 0b111111100, 10, 0.2), S.ServeState(pops[1], 0b1111111000000, 10, 0.25)]
+    reqs = []
+    for i in range(10):
+        st = states[i % 2]
+        m = int(rng.integers(1, 900))
+        reqs.append((st, torch.from_numpy(rng.random((m, st.d)).astype(np.float32)).cuda(), 1 + (i // 2) % 2))
+    alone = []
+    for st, a, meth in reqs:
+        j = S.AlertJob.alloc(st, a, method=meth)
+        S.snaps_alerts_score([j])
+        alone.append(j)
+    mixed = [S.AlertJob.alloc(st, a, method=meth) for st, a, meth in reqs]
+    S.snaps_alerts_score(mixed)
+    torch.cuda.synchronize()
+    for x, y in zip(alone, mixed):
+        for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+            assert torch.equal(getattr(x, key), getattr(y, key)), key

@@ -173,3 +173,91 @@ def test_far_candidates_do_not_pass(d):
         L = limit(norm(q), f32(dd / 4.0), d)
         exact, loss = worst_score(q, p, L, d)
         assert exact + loss < -h_of(p, d)
+
+
+# The alert kernel's object side (a pair must also pass when dd < rk_p, the
+# population object's own k-th neighbour dd): the column's pass threshold is
+# -h_p + min(0, A_q + B_p) with A_q = (1/2 + c16 - K u) T_q - 2 K u qn and
+# B_p = -(1/2 + c16 + K u) rk_p - 4 u |h_p| (K = 64 NS + 32, twice what the
+# accumulation bound of both limits needs), the alert's accumulator carrying
+# its own limit L_q = limit(qn, T_q).
+
+
+def k_slack(d):
+    return 64 * steps(d) + 32
+
+
+def object_side_threshold(qn, T, rk, hp, d):
+    K = k_slack(d)
+    c16 = f32((139 * steps(d) + 120 + d) * U)
+    ca = f32(f32(0.5 + c16) - f32(K * U))
+    cr = f32(f32(0.5 + c16) + f32(K * U))
+    aq = fma32(ca, T, f32(f32(-2.0 * K * U) * qn))
+    bp = fma32(-cr, rk, f32(-4 * U * abs(hp)))
+    return f32(-hp + min(0.0, f32(aq + bp)))
+
+
+@pytest.mark.parametrize("d", [2, 3, 5, 8, 10, 11, 15, 16])
+def test_object_side_passes_every_counting_object(d):
+    """Every object whose own k-th dd exceeds its direct-form distance to the
+    alert passes, whatever the alert's own threshold (down to 0)."""
+    rng = np.random.default_rng(1300 + d)
+    for kind in KINDS:
+        for q, p in pairs(kind, d, rng, 40):
+            dd = direct(q, p)
+            rk = float(np.nextafter(np.float32(dd), np.float32(np.inf)))     # dd < rk, tightest
+            hp = h_of(p, d)
+            for T in (0.0, f32(dd / 8), f32(dd * 0.999), rk, f32(4 * rk + 1e-3)):
+                L = limit(norm(q), T, d)
+                exact, loss = worst_score(q, p, L, d)
+                x = object_side_threshold(norm(q), T, rk, hp, d)
+                assert exact - loss >= x, f"{kind} d={d} T={T}: a counting object fails by {x - exact + loss:.3e}"
+
+
+def object_side_variant(qn, T, rk, hp, d, mode):
+    """Two plausible mistakes: B without its rk term (the object side adds
+    nothing to the alert side), and A taken from a larger threshold than the
+    row's own (the block row's largest instead of its smallest)."""
+    K = k_slack(d)
+    c16 = f32((139 * steps(d) + 120 + d) * U)
+    ca = f32(f32(0.5 + c16) - f32(K * U))
+    cr = f32(f32(0.5 + c16) + f32(K * U))
+    if mode == "largest_row":
+        T = f32(4 * T + 4 * rk)
+    aq = fma32(ca, T, f32(f32(-2.0 * K * U) * qn))
+    bp = f32(-4 * U * abs(hp)) if mode == "no_rk" else fma32(-cr, rk, f32(-4 * U * abs(hp)))
+    return f32(-hp + min(0.0, f32(aq + bp)))
+
+
+@pytest.mark.parametrize("mode", ["no_rk", "largest_row"])
+@pytest.mark.parametrize("d", [3, 8, 15])
+def test_object_side_check_catches_mistakes(d, mode):
+    rng = np.random.default_rng(1400 + d)
+    fails = 0
+    for kind in ("unit", "large_norm", "edge"):
+        for q, p in pairs(kind, d, rng, 40):
+            dd = direct(q, p)
+            rk = float(np.nextafter(np.float32(dd), np.float32(np.inf)))
+            T = f32(dd / 8)
+            L = limit(norm(q), T, d)
+            exact, loss = worst_score(q, p, L, d)
+            fails += (exact - loss) < object_side_variant(norm(q), T, rk, h_of(p, d), d, mode)
+    assert fails > 0
+
+
+@pytest.mark.parametrize("d", [3, 8, 15])
+def test_object_side_is_not_vacuous(d):
+    """An object at four times its own k-th dd from the alert (alert
+    threshold 0) fails the object side even with the most favourable
+    accumulation, once that dd is above the widening's scale (10^-3 qn)."""
+    rng = np.random.default_rng(1500 + d)
+    tested = 0
+    for q, p in pairs("unit", d, rng, 40):
+        dd = direct(q, p)
+        if dd < 1e-3 * norm(q):
+            continue
+        L = limit(norm(q), 0.0, d)
+        exact, loss = worst_score(q, p, L, d)
+        assert exact + loss < object_side_threshold(norm(q), 0.0, f32(dd / 4), h_of(p, d), d)
+        tested += 1
+    assert tested >= 20
