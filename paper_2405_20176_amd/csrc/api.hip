@@ -1146,17 +1146,15 @@ struct ServeLayout {
 
 // Kernel of one alert job: 1 = one wavefront per alert (k_alerts), 2 = the
 // matrix-core cross-join of 64-alert groups (k_alerts_mfma).  Automatic
-// choice: the matrix cores from kAlertMfmaMinD dimensions, where the
-// per-alert walk meets most tiles (measured on 10^6-object states with
-// 16..10^4 alerts per request: at d = 7 the matrix cores are 1.3-3.5x
-// faster, at d = 15 10-18x; at d = 6 faster only below ~500 alerts, at
-// d <= 5 slower, the per-alert index culling there being the better tool).
-constexpr int kAlertMfmaMinD = 7;
-
+// choice: the matrix cores from d = 7, and at d = 6 up to 1,024 alerts,
+// where the per-alert walk meets most tiles (measured on 10^6-object states
+// with 16..10^4 alerts per request: at d = 7 the matrix cores are 2.2-7x
+// faster, at d = 15 10-34x; at d = 6 3x faster for small requests and up
+// to 1.4x slower for 10^4 alerts; at d <= 5 the per-alert index culling is
+// the better tool).
 int alert_method(int method, int d, int m) {
-    (void)m;
     if (method != 0) return method;
-    return d >= kAlertMfmaMinD ? 2 : 1;
+    return d >= 7 || (d == 6 && m <= 1024) ? 2 : 1;
 }
 
 ServeLayout serve_layout(int64_t n, int d, int k) {

@@ -313,17 +313,25 @@ hipError_t launch_alerts(int D, int kc, const AlertArgs& a, hipStream_t s) {
 }
 
 // Merges the slices' partial results of one group of 64 alerts (one lane
-// per alert), in slice order, and writes the scores and rank positions
-// exactly as k_alerts does: the k nearest distances are the k smallest of
-// the slices' lists, and the kNN mean is lane 0's result of k_alerts'
-// wavefront sum (each lane i of the first 32 holding slot i, the others 0),
-// step by step.
+// per alert) and writes the scores and rank positions exactly as k_alerts
+// does: the k nearest distances are the k smallest of the slices' lists, and
+// the kNN mean is lane 0's result of k_alerts' wavefront sum (each lane i of
+// the first 32 holding slot i, the others 0), step by step.  Wavefront w of
+// the kMergeWaves takes the slices w, w + kMergeWaves, ... in order, the
+// next slice's values loaded while the current one is merged; wavefront 0
+// then adds the others' results in wavefront order, so the float64 eps sum
+// is taken in a fixed order for a given slice count.
+constexpr int kMergeWaves = 4;
+
 template <int KC>
-__global__ __launch_bounds__(64) void k_alerts_merge(AlertArgs A) {
+__global__ __launch_bounds__(64 * kMergeWaves) void k_alerts_merge(AlertArgs A) {
     using namespace alert_detail;
     constexpr int KS = KC;
+    constexpr int NV = KS + 4;                   // values of one partial result per lane
     static_assert(KS <= 32, "the kNN mean's reduction order assumes at most 32 slots");
-    const int lane = threadIdx.x;
+    __shared__ float s_part[kMergeWaves - 1][NV][kTile];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int g = blockIdx.x;
     if (g >= A.merge_prefix[A.n_jobs]) return;
     int lo = 0, hi = A.n_jobs;
@@ -334,14 +342,16 @@ __global__ __launch_bounds__(64) void k_alerts_merge(AlertArgs A) {
     const AlertJob& J = A.jobs[lo];
     const int gi = g - A.merge_prefix[lo];
     const int ai = gi * kTile + lane;
-    if (ai >= J.m) return;
+    const bool live = ai < J.m;
     const ServeState* St = J.st;
     const int k = St->k;
     if (St->d != A.d || k < 1 || k > KS) {       // state of another shape: flag the alert
-        J.eps_count[ai] = -1;
-        J.indeg[ai] = -1;
-        J.eps_mean[ai] = NAN;
-        J.knn_mean[ai] = NAN;
+        if (wv == 0 && live) {
+            J.eps_count[ai] = -1;
+            J.indeg[ai] = -1;
+            J.eps_mean[ai] = NAN;
+            J.knn_mean[ai] = NAN;
+        }
         return;
     }
     const int nsl = A.slices[lo];
@@ -351,20 +361,50 @@ __global__ __launch_bounds__(64) void k_alerts_merge(AlertArgs A) {
     for (int j = 0; j < KS; ++j) kd[j] = j < KS - k ? -INFINITY : INFINITY;
     int cnt = 0, deg = 0;
     double sum = 0.0;
-    for (int s = 0; s < nsl; ++s) {
-        const float* ps = part + (int64_t)s * alert_part_floats(KS);
+    auto fetch = [&](int sl, float (&v)[NV]) {
+        const float* ps = part + (int64_t)sl * alert_part_floats(KS) + lane;
 #pragma unroll
-        for (int j = 0; j < KS; ++j) {
-            if (j >= KS - k) {
-                const float v = ps[j * kTile + lane];
-                if (v < kd[KS - 1]) alert_mfma_detail::dist_insert<KS>(kd, v);
+        for (int j = 0; j < NV; ++j) v[j] = ps[j * kTile];
+    };
+    auto merge = [&](const float (&v)[NV]) {
+#pragma unroll
+        for (int j = 0; j < KS; ++j)
+            if (j >= KS - k && v[j] < kd[KS - 1]) alert_mfma_detail::dist_insert<KS>(kd, v[j]);
+        cnt += __float_as_int(v[KS]);
+        deg += __float_as_int(v[KS + 1]);
+        const unsigned long long lo32 = (unsigned)__float_as_int(v[KS + 2]);
+        const unsigned long long hi32 = (unsigned)__float_as_int(v[KS + 3]);
+        sum += __longlong_as_double((long long)((hi32 << 32) | lo32));
+    };
+    if (wv < nsl) {
+        float cur[NV], nxt[NV];
+        fetch(wv, cur);
+        for (int sl = wv; sl < nsl; sl += kMergeWaves) {
+            const bool more = sl + kMergeWaves < nsl;
+            if (more) fetch(sl + kMergeWaves, nxt);
+            merge(cur);
+            if (more) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j) cur[j] = nxt[j];
             }
         }
-        cnt += __float_as_int(ps[KS * kTile + lane]);
-        deg += __float_as_int(ps[(KS + 1) * kTile + lane]);
-        const unsigned long long lo32 = (unsigned)__float_as_int(ps[(KS + 2) * kTile + lane]);
-        const unsigned long long hi32 = (unsigned)__float_as_int(ps[(KS + 3) * kTile + lane]);
-        sum += __longlong_as_double((long long)((hi32 << 32) | lo32));
+    }
+    if (wv > 0) {
+        const long long sb = __double_as_longlong(sum);
+#pragma unroll
+        for (int j = 0; j < KS; ++j) s_part[wv - 1][j][lane] = kd[j];
+        s_part[wv - 1][KS][lane] = __int_as_float(cnt);
+        s_part[wv - 1][KS + 1][lane] = __int_as_float(deg);
+        s_part[wv - 1][KS + 2][lane] = __int_as_float((int)(unsigned)(sb & 0xffffffffLL));
+        s_part[wv - 1][KS + 3][lane] = __int_as_float((int)(sb >> 32));
+    }
+    __syncthreads();
+    if (wv != 0 || !live) return;
+    for (int w = 1; w < kMergeWaves; ++w) {
+        float v[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = s_part[w - 1][j][lane];
+        merge(v);
     }
     float v[32];
 #pragma unroll
@@ -401,7 +441,8 @@ hipError_t launch_alerts_mfma(int D, int kc, const AlertArgs& a, hipStream_t s) 
     hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(blocks), dim3(64 * kAlertMfmaWaves),
                                    args, 0, s);
     if (e != hipSuccess) return e;
-    return hipLaunchKernel(reinterpret_cast<const void*>(mfn), dim3(a.merge_prefix[a.n_jobs]), dim3(64), args, 0, s);
+    return hipLaunchKernel(reinterpret_cast<const void*>(mfn), dim3(a.merge_prefix[a.n_jobs]), dim3(64 * kMergeWaves), args,
+                           0, s);
 }
 
 }  // namespace snaps

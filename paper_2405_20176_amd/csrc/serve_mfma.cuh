@@ -13,7 +13,9 @@
 // k-th neighbour distance).  Per dimension the boxes' gap is at most each
 // pair's own difference (the same subtractions with the alert replaced by
 // its box's near corner, and float rounding is monotone), so a skipped tile
-// holds no pair that matters.  A kept tile's rows and k-th distances are
+// holds no pair that matters.  The wavefronts of a workgroup share, through
+// LDS, the smallest k-th distance any of them has found for each alert and
+// screen with it (the final k-th distance is at most that).  A kept tile's rows and k-th distances are
 // copied into LDS, and its 64 x 64 pairs are screened by the half-precision
 // contraction of the matrix-core join (join_mfma.cuh), rows being alerts.
 // A pair passes if it can matter to either side:
@@ -94,6 +96,11 @@ __global__ __launch_bounds__(64 * kAlertMfmaWaves) void k_alerts_mfma(AlertArgs 
     __shared__ __align__(16) float s_rk0[W][kTile];
     __shared__ __align__(16) float s_rk1[W][kTile];
     __shared__ float s_part[KS + 4][kTile];      // one wavefront's partial results, for the merge
+    // Smallest k-th distance any wavefront of the workgroup has found for
+    // each alert (float bits; the values are >= 0, so integer order is float
+    // order).  The final k-th distance is at most each of them, so every
+    // wavefront may screen with the smallest.
+    __shared__ unsigned s_kth[kTile];
 
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -118,6 +125,8 @@ __global__ __launch_bounds__(64 * kAlertMfmaWaves) void k_alerts_mfma(AlertArgs 
     const ServeState* St = J.st;
     const int k = St->k;
     if (St->d != D || k < 1 || k > KS) return;   // state of another shape: the merge flags the alerts
+    if (wv == 0) s_kth[lane] = 0x7F800000u;      // +inf
+    __syncthreads();
     // This slice's run of tiles.
     const int per = (St->ntiles + nsl - 1) / nsl;
     const int t_lo = sl * per;
@@ -137,9 +146,12 @@ __global__ __launch_bounds__(64 * kAlertMfmaWaves) void k_alerts_mfma(AlertArgs 
     for (int j = 0; j < KS; ++j) kd[j] = j < KS - k ? -INFINITY : INFINITY;
     int cnt = 0, deg = 0;
     double sum = 0.0;
-    // A pad lane has nothing in reach (-inf threshold: its limit is +inf and
-    // its scores never pass; excluded from the culls and from A_min).
-    float thr = qpad ? -INFINITY : fmaxf(kd[KS - 1], eps2);
+    // kb: the smallest k-th distance known for the alert (this wavefront's
+    // own or another's).  A pad lane has nothing in reach (-inf threshold:
+    // its limit is +inf and its scores never pass; excluded from the culls
+    // and from A_min).
+    float kb = INFINITY;
+    float thr = qpad ? -INFINITY : fmaxf(kb, eps2);
     float qn = 0.f;
 #pragma unroll
     for (int f = 0; f < D; ++f) qn = fmaf(q[f], q[f], qn);
@@ -242,6 +254,16 @@ __global__ __launch_bounds__(64 * kAlertMfmaWaves) void k_alerts_mfma(AlertArgs 
 
     auto process = [&](int tv, const float* rows_l, const float* rk_l) {
         const int rows = tv >> kRowShift;
+        {   // take up a smaller k-th distance found by another wavefront
+            const float sk = __uint_as_float(s_kth[lane]);
+            const bool tighter = !qpad && sk < kb;
+            if (tighter) {
+                kb = sk;
+                thr = fmaxf(kb, eps2);
+                lim = f16_limit<D>(qn, thr);
+            }
+            if (__any(tighter)) refresh();
+        }
         bool hit = false, all = unit_all;
         unsigned mk[2] = {0u, 0u};
 #pragma unroll
@@ -313,9 +335,11 @@ __global__ __launch_bounds__(64 * kAlertMfmaWaves) void k_alerts_mfma(AlertArgs 
                     moved = true;
                 }
             }
-            if (moved) {
-                thr = fmaxf(kd[KS - 1], eps2);
+            if (moved && kd[KS - 1] < kb) {
+                kb = kd[KS - 1];
+                thr = fmaxf(kb, eps2);
                 lim = f16_limit<D>(qn, thr);
+                atomicMin(&s_kth[lane], __float_as_uint(kb));
             }
             if (__any(moved)) refresh();
         }
