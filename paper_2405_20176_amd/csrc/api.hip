@@ -1296,7 +1296,7 @@ size_t snaps_alerts_workspace_bytes(const snaps_alert_job* jobs, int32_t n_jobs,
         const snaps_alert_job& a = jobs[i];
         if (a.m <= 0 || alert_method(a.method, d, a.m) != 2) continue;
         const int64_t groups = (a.m + kTile - 1) / kTile;
-        bytes += align_up((size_t)(groups * alert_slices(a.m) * alert_part_floats(kc)) * sizeof(float));
+        bytes += align_up((size_t)(groups * alert_slices(a.m, d) * alert_part_floats(kc)) * sizeof(float));
     }
     return bytes;
 }
@@ -1351,7 +1351,7 @@ int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, i
                     return fail(SNAPS_EINVAL, "more than 2^31 alerts in one call");
                 if (mfma) {
                     const int64_t g = (a.m + kTile - 1) / kTile;
-                    const int sl = alert_slices(a.m);
+                    const int sl = alert_slices(a.m, d);
                     aa.slices[i] = sl;
                     aa.part_off[i] = (int64_t)part_at;
                     part_at += align_up((size_t)(g * sl * alert_part_floats(kc)) * sizeof(float)) / sizeof(float);

@@ -438,7 +438,7 @@ hipError_t launch_alerts_mfma(int D, int kc, const AlertArgs& a, hipStream_t s) 
     if (blocks <= 0) return hipSuccess;
     AlertArgs copy = a;
     void* args[] = {&copy};
-    hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(blocks), dim3(64 * kAlertMfmaWaves),
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(blocks), dim3(64 * alert_mfma_waves(D)),
                                    args, 0, s);
     if (e != hipSuccess) return e;
     return hipLaunchKernel(reinterpret_cast<const void*>(mfn), dim3(a.merge_prefix[a.n_jobs]), dim3(64 * kMergeWaves), args,

@@ -2,7 +2,7 @@
 // cross-join of groups of 64 alerts against the population's tiles.
 //
 // A workgroup takes one group of 64 alerts of one job, one alert per lane in
-// each of its W = kAlertMfmaWaves wavefronts, and one slice (a run of
+// each of its W = alert_mfma_waves(d) wavefronts, and one slice (a run of
 // consecutive tiles) of the population, which it splits among its
 // wavefronts: wavefront w takes the slice's tiles w, w + W, w + 2 W, ...
 // It tests the next 64 of its tiles at once, one per lane, with the group's
@@ -70,7 +70,7 @@ __device__ __forceinline__ void dist_insert(float (&kd)[KS], float v) {
 }  // namespace alert_mfma_detail
 
 template <int D, int KC>
-__global__ __launch_bounds__(64 * kAlertMfmaWaves) void k_alerts_mfma(AlertArgs A) {
+__global__ __launch_bounds__(64 * alert_mfma_waves(D)) void k_alerts_mfma(AlertArgs A) {
     using namespace mfma_detail;
     using namespace alert_detail;
     using namespace alert_mfma_detail;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(64 * kAlertMfmaWaves) void k_alerts_mfma(AlertArgs 
     using Sp = Split<D>;
     constexpr int M = Sp::M;
     constexpr int NS = Sp::NS;
-    constexpr int W = kAlertMfmaWaves;
+    constexpr int W = alert_mfma_waves(D);
     constexpr int kRowShift = 26;                // walk entry: tile | block rows in reach << 26
     constexpr int kTileMask = (1 << kRowShift) - 1;
     constexpr float kSlack = (float)(64 * NS + 32) * kU;

@@ -198,21 +198,24 @@ struct AlertArgs {
     int32_t n_jobs, d;
 };
 // Matrix-core alert scoring: the population of a job is cut into `slices`
-// contiguous runs of tiles; one workgroup of kAlertMfmaWaves wavefronts per
-// (group of 64 alerts, slice) splits the slice among its wavefronts and
+// contiguous runs of tiles; one workgroup of alert_mfma_waves(d) wavefronts
+// per (group of 64 alerts, slice) splits the slice among its wavefronts and
 // writes the slice's partial results; one wavefront per group then merges
 // them in slice order.  The slice count depends only on the job's alert
-// count, so the scores of a job do not depend on the other jobs of a call.
-// (Measured on 10^6-object states, d = 6..15: eight wavefronts per group and
-// about 1,024 workgroups per job beat sixteen wavefronts or 512 workgroups
-// by up to 25 % on 10^4-alert requests, and equal them on small ones.)
-constexpr int kAlertMfmaWaves = 8;
-constexpr int kAlertTargetBlocks = 1024;       // workgroups aimed at per job
-constexpr int kAlertMaxSlices = 64;
-inline int alert_slices(int m) {
+// count and d, so the scores of a job do not depend on the other jobs of a
+// call.  (Measured on 10^6-object states, d = 6..15: eight wavefronts per
+// workgroup and about 8,192 wavefronts per job; at d = 15-16, where the two
+// tile buffers of eight wavefronts leave room for one workgroup per compute
+// unit, four wavefronts per workgroup, 1.2-1.4x faster on 4,096-10^4-alert
+// requests.  Sixteen wavefronts, or 4,096 per job, were up to 25 % slower.)
+__host__ __device__ constexpr int alert_mfma_waves(int d) { return row_stride(d) > 16 ? 4 : 8; }
+constexpr int kAlertTargetWaves = 8192;
+inline int alert_slices(int m, int d) {
+    const int w = alert_mfma_waves(d);
     const int groups = (m + kTile - 1) / kTile;
-    const int s = (kAlertTargetBlocks + groups - 1) / groups;
-    return s < 1 ? 1 : (s > kAlertMaxSlices ? kAlertMaxSlices : s);
+    const int s = (kAlertTargetWaves / w + groups - 1) / groups;
+    const int cap = 512 / w;
+    return s < 1 ? 1 : (s > cap ? cap : s);
 }
 // Floats of one partial result: KS kNN slots, count, in-degree, float64 sum, for 64 lanes.
 __host__ __device__ constexpr int64_t alert_part_floats(int kc) { return (int64_t)(kc + 4) * kTile; }
