@@ -303,12 +303,14 @@ def _assert_kernels_agree(w, t):
 
 @pytest.mark.parametrize("n,d,k,m", [(5000, 2, 5, 1), (20000, 6, 10, 63), (20000, 9, 20, 65), (70000, 12, 32, 700),
                                      (30000, 15, 10, 130), (8000, 16, 5, 64), (3000, 7, 10, 1000),
-                                     (150000, 10, 10, 200)])
+                                     (150000, 10, 10, 200), (20000, 15, 32, 100), (12000, 16, 20, 300),
+                                     (40000, 11, 10, 5000)])
 def test_matrix_core_alerts_match_wavefront(S, n, d, k, m):
     """Ragged alert counts (one alert, 63, 64, 65 ...), every k class, d from
-    2 to 16, populations from one to 37 super-tiles: alerts inside the bulk,
-    exact copies of population objects (distance 0), far outside, and on the
-    edge of the bulk."""
+    2 to 16 (four wavefronts per workgroup at d = 15-16, eight below), 13 to
+    128 population slices, populations from one to 37 super-tiles: alerts
+    inside the bulk, exact copies of population objects (distance 0), far
+    outside, and on the edge of the bulk."""
     rng = np.random.default_rng(n + 31 * d + m)
     job = G.gen_c3_jobs(4)[3]
     x = G.gen_c3_population(job, n=n)
