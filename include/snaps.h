@@ -341,7 +341,7 @@ typedef struct {
  *             with every passing pair re-evaluated exactly; the population
  *             is cut into slices whose partial results are merged in a
  *             fixed order;
- *   method 0: 2 for d >= 7 and for d = 6 with at most 1,024 alerts, else 1.
+ *   method 0: 2 for d >= 6 and for d = 5 with at most 512 alerts, else 1.
  * Both give identical eps counts, in-degrees, kNN means and their rank
  * positions; the eps mean (a float64 sum taken in another order) may differ
  * in the last float bit.  A job's kernel and slicing depend only on its own

@@ -1146,15 +1146,15 @@ struct ServeLayout {
 
 // Kernel of one alert job: 1 = one wavefront per alert (k_alerts), 2 = the
 // matrix-core cross-join of 64-alert groups (k_alerts_mfma).  Automatic
-// choice: the matrix cores from d = 7, and at d = 6 up to 1,024 alerts,
-// where the per-alert walk meets most tiles (measured on 10^6-object states
-// with 16..10^4 alerts per request: at d = 7 the matrix cores are 2.2-7x
-// faster, at d = 15 10-34x; at d = 6 3x faster for small requests and up
-// to 1.4x slower for 10^4 alerts; at d <= 5 the per-alert index culling is
-// the better tool).
+// choice: the matrix cores from d = 6, and at d = 5 up to 512 alerts, where
+// the per-alert walk meets most tiles (measured on 10^6-object states with
+// 16..10^4 alerts per request: at d = 6 the matrix cores are 1.2-4.6x
+// faster, at d = 10 7.6-21x, at d = 15 10-33x; at d = 5 1.6-1.9x faster up
+// to 256 alerts and 0.8x from 1,024; at d <= 4 the per-alert index culling
+// is the better tool).
 int alert_method(int method, int d, int m) {
     if (method != 0) return method;
-    return d >= 7 || (d == 6 && m <= 1024) ? 2 : 1;
+    return d >= 6 || (d == 5 && m <= 512) ? 2 : 1;
 }
 
 ServeLayout serve_layout(int64_t n, int d, int k) {
@@ -1288,17 +1288,34 @@ int snaps_serve_state_outputs(const void* state, int64_t n, int32_t d, int32_t k
     return SNAPS_OK;
 }
 
-size_t snaps_alerts_workspace_bytes(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k) {
-    if (n_jobs < 1 || !jobs || d < 2 || d > kMaxD || k < 1 || k > kMaxK) return 0;
-    const int kc = kc_class(k);
-    size_t bytes = 0;
+namespace {
+
+// Matrix-core alert jobs' workspace: the slices' partial results of every
+// such job, then one k-th distance bound per alert slot (64 per group),
+// shared by the workgroups of a group.
+struct AlertWs {
+    size_t part_bytes = 0, bound_count = 0;
+    size_t bytes() const { return part_bytes + align_up(bound_count * sizeof(uint32_t)); }
+};
+
+AlertWs alert_ws(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int kc) {
+    AlertWs w;
     for (int i = 0; i < n_jobs; ++i) {
         const snaps_alert_job& a = jobs[i];
         if (a.m <= 0 || alert_method(a.method, d, a.m) != 2) continue;
         const int64_t groups = (a.m + kTile - 1) / kTile;
-        bytes += align_up((size_t)(groups * alert_slices(a.m, d) * alert_part_floats(kc)) * sizeof(float));
+        w.part_bytes += align_up((size_t)(groups * alert_slices(a.m, d) * alert_part_floats(kc)) * sizeof(float));
+        w.bound_count += (size_t)groups * kTile;
     }
-    return bytes;
+    return w;
+}
+
+}  // namespace
+
+size_t snaps_alerts_workspace_bytes(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k) {
+    if (n_jobs < 1 || !jobs || d < 2 || d > kMaxD || k < 1 || k > kMaxK) return 0;
+    const AlertWs w = alert_ws(jobs, n_jobs, d, kc_class(k));
+    return w.bound_count ? w.bytes() : 0;
 }
 
 int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k, void* ws, size_t ws_bytes,
@@ -1318,9 +1335,17 @@ int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, i
     if (need > 0 && !ws) return fail(SNAPS_EINVAL, "workspace is NULL (%zu bytes needed)", need);
     if (ws_bytes < need) return fail(SNAPS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
     const int kc = kc_class(k);
+    const AlertWs aws = alert_ws(jobs, n_jobs, d, kc);
+    uint32_t* bounds = aws.bound_count ? reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + aws.part_bytes) : nullptr;
+    if (bounds) {
+        if (aws.bound_count > (size_t)INT32_MAX) return fail(SNAPS_EINVAL, "too many alerts in one call");
+        hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(bounds), (int32_t)aws.bound_count, 0x7F800000, s);
+        if (e != hipSuccess) return hip_fail(e, "alert bound fill launch");
+    }
     // Each job's kernel and slice count depend only on its own method, d and
     // size, so an alert's scores do not depend on the other jobs of the call.
     size_t part_at = 0;                          // floats into ws
+    size_t bound_at = 0;                         // bound slots
     for (int mfma = 0; mfma < 2; ++mfma) {
         std::vector<int> sel;
         for (int i = 0; i < n_jobs; ++i)
@@ -1332,6 +1357,7 @@ int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, i
             aa.n_jobs = nb;
             aa.d = d;
             aa.part = static_cast<float*>(ws);
+            aa.bounds = bounds;
             for (int i = 0; i < nb; ++i) {
                 const snaps_alert_job& a = jobs[sel[b + i]];
                 AlertJob& J = aa.jobs[i];
@@ -1355,6 +1381,8 @@ int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, i
                     aa.slices[i] = sl;
                     aa.part_off[i] = (int64_t)part_at;
                     part_at += align_up((size_t)(g * sl * alert_part_floats(kc)) * sizeof(float)) / sizeof(float);
+                    aa.bound_off[i] = (int64_t)bound_at;
+                    bound_at += (size_t)g * kTile;
                     blocks += g * sl;
                     groups += g;
                     if (blocks > INT32_MAX) return fail(SNAPS_EINVAL, "too many alert groups in one call");

@@ -14,8 +14,10 @@
 // pair's own difference (the same subtractions with the alert replaced by
 // its box's near corner, and float rounding is monotone), so a skipped tile
 // holds no pair that matters.  The wavefronts of a workgroup share, through
-// LDS, the smallest k-th distance any of them has found for each alert and
-// screen with it (the final k-th distance is at most that).  A kept tile's rows and k-th distances are
+// LDS, the smallest k-th distance any of them has found for each alert, and
+// the workgroups of a group through a slot per alert in global memory; each
+// screens with the smallest it has seen (the final k-th distance is at most
+// that).  A kept tile's rows and k-th distances are
 // copied into LDS, and its 64 x 64 pairs are screened by the half-precision
 // contraction of the matrix-core join (join_mfma.cuh), rows being alerts.
 // A pair passes if it can matter to either side:
@@ -70,7 +72,7 @@ __device__ __forceinline__ void dist_insert(float (&kd)[KS], float v) {
 }  // namespace alert_mfma_detail
 
 template <int D, int KC>
-__global__ __launch_bounds__(64 * alert_mfma_waves(D)) void k_alerts_mfma(AlertArgs A) {
+__device__ __forceinline__ void alerts_mfma_body(const AlertArgs& A) {
     using namespace mfma_detail;
     using namespace alert_detail;
     using namespace alert_mfma_detail;
@@ -99,7 +101,9 @@ __global__ __launch_bounds__(64 * alert_mfma_waves(D)) void k_alerts_mfma(AlertA
     // Smallest k-th distance any wavefront of the workgroup has found for
     // each alert (float bits; the values are >= 0, so integer order is float
     // order).  The final k-th distance is at most each of them, so every
-    // wavefront may screen with the smallest.
+    // wavefront may screen with the smallest.  The same bound is published,
+    // by device-scope atomic minimum, to the group's slot in A.bounds, where
+    // the workgroups of the group's other slices take it up.
     __shared__ unsigned s_kth[kTile];
 
     const int lane = threadIdx.x & 63;
@@ -127,6 +131,7 @@ __global__ __launch_bounds__(64 * alert_mfma_waves(D)) void k_alerts_mfma(AlertA
     if (St->d != D || k < 1 || k > KS) return;   // state of another shape: the merge flags the alerts
     if (wv == 0) s_kth[lane] = 0x7F800000u;      // +inf
     __syncthreads();
+    unsigned* const gbound = A.bounds + A.bound_off[lo] + (int64_t)gi * kTile + lane;
     // This slice's run of tiles.
     const int per = (St->ntiles + nsl - 1) / nsl;
     const int t_lo = sl * per;
@@ -254,6 +259,9 @@ __global__ __launch_bounds__(64 * alert_mfma_waves(D)) void k_alerts_mfma(AlertA
 
     auto process = [&](int tv, const float* rows_l, const float* rk_l) {
         const int rows = tv >> kRowShift;
+        // The bound the group's other slices have published, read now and
+        // taken up after this tile (so the load's latency is hidden).
+        const unsigned gb = __hip_atomic_load(gbound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         {   // take up a smaller k-th distance found by another wavefront
             const float sk = __uint_as_float(s_kth[lane]);
             const bool tighter = !qpad && sk < kb;
@@ -310,8 +318,8 @@ __global__ __launch_bounds__(64 * alert_mfma_waves(D)) void k_alerts_mfma(AlertA
                 }
             }
         }
+        bool moved = false;
         if (hit || all) {
-            bool moved = false;
             unsigned long long mine = all ? ~0ull : (((unsigned long long)mk[1] << 32) | mk[0]);
             if (qpad) mine = 0ull;
             while (mine) {
@@ -340,9 +348,17 @@ __global__ __launch_bounds__(64 * alert_mfma_waves(D)) void k_alerts_mfma(AlertA
                 thr = fmaxf(kb, eps2);
                 lim = f16_limit<D>(qn, thr);
                 atomicMin(&s_kth[lane], __float_as_uint(kb));
+                __hip_atomic_fetch_min(gbound, __float_as_uint(kb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (__any(moved)) refresh();
         }
+        const bool from_group = !qpad && __uint_as_float(gb) < kb;
+        if (from_group) {
+            kb = __uint_as_float(gb);
+            thr = fmaxf(kb, eps2);
+            lim = f16_limit<D>(qn, thr);
+            atomicMin(&s_kth[lane], gb);
+        }
+        if (__any(moved) || __any(from_group)) refresh();
     };
 
     float* const r0 = s_rows0[wv];
@@ -410,11 +426,30 @@ __global__ __launch_bounds__(64 * alert_mfma_waves(D)) void k_alerts_mfma(AlertA
     part[(KS + 3) * kTile + lane] = __int_as_float((int)(sb >> 32));
 }
 
+template <int D, int KC>
+__global__ __launch_bounds__(64 * alert_mfma_waves(D)) void k_alerts_mfma(AlertArgs A) {
+    alerts_mfma_body<D, KC>(A);
+}
+
+// The same kernel held to 128 VGPRs (four wavefronts per SIMD, two
+// eight-wavefront workgroups per compute unit) for k <= 10 with eight
+// wavefronts, where it needs at most a few more (d = 14: 129 VGPRs, three
+// wavefronts per SIMD and one workgroup per compute unit otherwise).
+template <int D, int KC>
+__global__ __launch_bounds__(64 * alert_mfma_waves(D)) __attribute__((amdgpu_waves_per_eu(4))) void
+k_alerts_mfma_o4(AlertArgs A) {
+    alerts_mfma_body<D, KC>(A);
+}
+
 template <int D>
 AlertKernel alert_mfma_kc(int kc) {
     switch (kc) {
-        case 5: return k_alerts_mfma<D, 5>;
-        case 10: return k_alerts_mfma<D, 10>;
+        case 5:
+            if constexpr (alert_mfma_waves(D) == 8) return k_alerts_mfma_o4<D, 5>;
+            else return k_alerts_mfma<D, 5>;
+        case 10:
+            if constexpr (alert_mfma_waves(D) == 8) return k_alerts_mfma_o4<D, 10>;
+            else return k_alerts_mfma<D, 10>;
         case 20: return k_alerts_mfma<D, 20>;
         case 32: return k_alerts_mfma<D, 32>;
     }

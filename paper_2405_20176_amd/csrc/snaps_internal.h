@@ -195,6 +195,10 @@ struct AlertArgs {
     int32_t slices[kAlertJobs];
     int64_t part_off[kAlertJobs];
     float* part;
+    // k-th distance bound per alert slot (float bits, +inf at the start),
+    // shared by the slices of a group; each job's first slot in `bounds`.
+    int64_t bound_off[kAlertJobs];
+    uint32_t* bounds;
     int32_t n_jobs, d;
 };
 // Matrix-core alert scoring: the population of a job is cut into `slices`
