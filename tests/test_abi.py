@@ -292,3 +292,61 @@ def test_static_scratch_entry_validation(lib):
     rc = lib.snaps_outlier_scores_static(ctypes.byref(bj), 1, None, None)
     assert rc == -2, lib.snaps_last_error()
     assert b"static scratch" in lib.snaps_last_error()
+
+
+def _alert_jobs(ms, methods):
+    from paper_2405_20176_amd.snaps import c_alert_job
+    arr = (c_alert_job * len(ms))()
+    for i, (m, meth) in enumerate(zip(ms, methods)):
+        arr[i].state = 0x1000                 # never dereferenced on the host
+        arr[i].alerts = 0x2000
+        arr[i].m = m
+        arr[i].method = meth
+        arr[i].eps_count, arr[i].eps_mean, arr[i].indeg, arr[i].knn_mean = 0x3000, 0x4000, 0x5000, 0x6000
+    return arr
+
+
+def _alert_ws_expected(ms, d, kc):
+    """The documented layout: per matrix-core job, groups x slices partial
+    results of (kc + 4) x 64 floats, then one 4-byte bound per alert slot,
+    each part rounded up to 256 bytes."""
+    align = lambda b: (b + 255) // 256 * 256
+    w = 4 if (d + 5) // 4 * 4 > 16 else 8     # wavefronts per workgroup
+    part, slots = 0, 0
+    for m in ms:
+        g = -(-m // 64)
+        sl = min(max(-(-(8192 // w) // g), 1), 512 // w)
+        part += align(g * sl * (kc + 4) * 64 * 4)
+        slots += g * 64
+    return part + align(slots * 4) if slots else 0
+
+
+def test_alert_workspace_and_kernel_choice(lib):
+    """Workspace of the matrix-core alert kernel, and which jobs run it:
+    method 2 always, method 1 never, method 0 from d = 6 and at d = 5 up to
+    512 alerts."""
+    ws = lambda ms, meths, d, k: lib.snaps_alerts_workspace_bytes(_alert_jobs(ms, meths), len(ms), d, k)
+    assert ws([1000], [0], 4, 10) == 0
+    assert ws([1000], [1], 10, 10) == 0
+    assert ws([1000], [2], 4, 10) == _alert_ws_expected([1000], 4, 10)
+    assert ws([1, 64, 65, 10000], [0] * 4, 6, 10) == _alert_ws_expected([1, 64, 65, 10000], 6, 10)
+    assert ws([100, 1000], [0, 0], 5, 10) == _alert_ws_expected([100], 5, 10)
+    assert ws([300], [0], 15, 20) == _alert_ws_expected([300], 15, 20)      # four wavefronts at d = 15
+    assert ws([300], [0], 15, 20) != _alert_ws_expected([300], 14, 20)
+    assert ws([0, 500], [2, 1], 12, 32) == 0                                # no alerts / per-alert kernel
+    assert ws([500], [0], 1, 10) == 0 and ws([500], [0], 8, 0) == 0       # invalid d, k
+
+
+def test_alert_score_validation(lib):
+    """snaps_alerts_score refuses, before any device work, an unknown method,
+    a missing workspace and one that is too small."""
+    jobs = _alert_jobs([200], [3])
+    assert lib.snaps_alerts_score(jobs, 1, 8, 10, None, 0, None) == -1
+    jobs = _alert_jobs([200], [2])
+    need = lib.snaps_alerts_workspace_bytes(jobs, 1, 8, 10)
+    assert need > 0
+    assert lib.snaps_alerts_score(jobs, 1, 8, 10, None, 0, None) == -1
+    assert lib.snaps_alerts_score(jobs, 1, 8, 10, ctypes.c_void_p(0x10000), need - 1, None) == -2
+    assert b"workspace" in lib.snaps_last_error()
+    bad = _alert_jobs([-1], [1])
+    assert lib.snaps_alerts_score(bad, 1, 8, 10, None, 0, None) == -1
