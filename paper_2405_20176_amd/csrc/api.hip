@@ -1,6 +1,7 @@
 // C ABI of libsnaps: argument validation, workspace layout, job tables and
 // the launch sequence of the similarity self-join passes.
 #include "snaps_internal.h"
+#include "serve_internal.h"
 #include "../../include/snaps.h"
 
 #include <algorithm>

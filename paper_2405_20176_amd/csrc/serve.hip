@@ -22,7 +22,7 @@
 // an eps neighbour or an object that would count the alert are read.  The
 // k best distances are kept sorted across lanes 0..KC-1; eps hits and
 // in-degree are wavefront ballots, the eps distance sum a float64 reduction.
-#include "snaps_internal.h"
+#include "serve_internal.h"
 #include "common.cuh"
 #include "keys.cuh"
 #include "join_kernel.cuh"

@@ -49,6 +49,7 @@
 #pragma once
 
 #include "join_mfma.cuh"
+#include "serve_internal.h"
 #include "keys.cuh"
 #include "serve.cuh"
 
