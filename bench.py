@@ -80,6 +80,61 @@ def cpu_baseline(x, masks, eps_tab, k):
             "extrapolated_s": total, "cpu_model": _cpu_model()}
 
 
+def alert_ab_bench(S, G, dev, sizes=(16, 256, 1024, 4096, 10000)):
+    """Per-request time of the two alert kernels (method 1: one wavefront per
+    alert; method 2: matrix-core cross-join of 64-alert groups) on one
+    10^6-object serving population, one catalogue subspace per d, alerts from
+    the serving generator (the largest request of that subspace, repeated
+    with a 10^-3 shift when short).  HIP events over 3 calls after a warm-up;
+    eps counts, in-degrees and kNN means compared between the kernels."""
+    import torch
+    w = G.gen_c4()
+    masks_tab, eps_tab = G.load_c4_eps()
+    x, lo, hi = w.population(0)
+    pop = S.Population.from_rows(x, device=dev)
+    del x
+    best = {}
+    for r in w.requests(60.0):
+        if r.pop != 0:
+            continue
+        d = bin(int(masks_tab[0, r.space])).count("1")
+        if d not in best or r.n_alerts > best[d].n_alerts:
+            best[d] = r
+    out = {}
+    for d, r in sorted(best.items()):
+        m_ = int(masks_tab[0, r.space])
+        st = S.ServeState(pop, m_, w.k, float(eps_tab[0, r.space]))
+        al = np.ascontiguousarray(w.alerts(r, lo, hi)[:, G.mask_features(m_)], dtype=np.float32)
+        while al.shape[0] < max(sizes):
+            al = np.concatenate([al, al + np.float32(1e-3)]).astype(np.float32)
+        row = {}
+        for m in sizes:
+            a = torch.tensor(al[:m], device=dev)
+            times, jobs = {}, {}
+            for meth in (1, 2):
+                job = S.AlertJob.alloc(st, a, method=meth)
+                S.snaps_alerts_score([job])
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(3):
+                    S.snaps_alerts_score([job])
+                e1.record()
+                torch.cuda.synchronize()
+                times[meth] = e0.elapsed_time(e1) / 3
+                jobs[meth] = job
+            same = all(torch.equal(getattr(jobs[1], key), getattr(jobs[2], key))
+                       for key in ("eps_count", "indeg", "knn_mean"))
+            row[str(m)] = {"per_alert_kernel_ms": times[1], "matrix_core_ms": times[2],
+                           "speedup": times[1] / times[2], "identical_counts_and_knn_mean": same}
+        out[str(d)] = row
+        log(f"alert A/B d={d}: " + ", ".join(f"m={m} {v['per_alert_kernel_ms']:.2f}/{v['matrix_core_ms']:.2f} ms"
+                                              for m, v in row.items()))
+        del st
+        torch.cuda.empty_cache()
+    return {"per_d": out, "population_n": pop.n, "k": w.k,
+            "what": "ms per request, one wavefront per alert / matrix cores, same state and alerts"}
+
+
 def serve_bench(S, G, dev, seconds: float, warmup_s: float = 10.0, n_streams: int = 4, plain_s: float = 20.0,
                 capacity_s: float = 10.0):
     """Served form: 4 resident populations of 1,000,000 objects (the serving
@@ -663,6 +718,8 @@ def main():
                     help="skip the per-dimensionality join breakdown (one eager pass per d after the timed steps)")
     ap.add_argument("--filter-ab", action="store_true",
                     help="after the per-d breakdown, time each d's join with the prefilter on the vector ALU and on the matrix cores")
+    ap.add_argument("--alert-ab", action="store_true",
+                    help="time both alert kernels per d and request size on one serving population (alert_ab)")
     ap.add_argument("--no-c2", dest="c2", action="store_false",
                     help="skip the LSST-scale population (5,000,000 objects, the full space + 105 two-feature spaces)")
     ap.add_argument("--c2-steps", type=int, default=1, help="timed steps of the LSST-scale population")
@@ -901,7 +958,7 @@ def main():
     if a.k_grid:
         result["k_grid_selection"] = k_grid_bench(S, pop, masks, n, dev, spaces=a.grid_spaces)
 
-    if a.c3 or a.c2 or a.serve_seconds > 0:
+    if a.c3 or a.c2 or a.serve_seconds > 0 or a.alert_ab:
         del plans, out_cnt, out_mean, out_deg, out_kmean, out_rank, out_ens
         torch.cuda.empty_cache()
     if a.c3:
@@ -910,6 +967,8 @@ def main():
         result["c2"] = c2_bench(S, G, dev, stream, a.c2_steps, a.lsst_k_grid)
     if a.serve_seconds > 0:
         result["serving"] = serve_bench(S, G, dev, a.serve_seconds)
+    if a.alert_ab:
+        result["alert_ab"] = alert_ab_bench(S, G, dev)
 
     if not a.no_cpu:
         cb = cpu_baseline(x, masks if not a.spaces else G.all_masks(), G.load_c1_eps(), k)
