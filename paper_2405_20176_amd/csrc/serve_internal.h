@@ -65,6 +65,7 @@ struct AlertArgs {
     uint32_t* bounds;
     int32_t n_jobs, d;
 };
+static_assert(sizeof(AlertArgs) <= 4096, "alert launches pass AlertArgs by value as kernel arguments");
 // Matrix-core alert scoring: the population of a job is cut into `slices`
 // contiguous runs of tiles; one workgroup of alert_mfma_waves(d) wavefronts
 // per (group of 64 alerts, slice) splits the slice among its wavefronts and
