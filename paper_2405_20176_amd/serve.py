@@ -170,10 +170,15 @@ class Batcher:
                 r = pending.popleft()
                 r.arrival += t0            # to the server clock
                 self.submit(r)
-            if not self.step() and pending:
-                wait = pending[0].arrival - (self.clock() - t0)
-                if wait > 0.0005:
-                    time.sleep(min(wait, 0.001))
+            if not self.step():
+                if self.inflight:
+                    # a batch on the device: poll again at once (a sleep
+                    # here would add up to its length to every completion)
+                    time.sleep(0)
+                elif pending:
+                    wait = pending[0].arrival - (self.clock() - t0)
+                    if wait > 0.0005:
+                        time.sleep(min(wait, 0.001))
 
     def latencies(self) -> np.ndarray:
         return np.array([r.done - r.arrival for r in self.finished if r.status == "done"])
