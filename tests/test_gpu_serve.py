@@ -386,3 +386,25 @@ def test_mixed_methods_in_one_call(S):
     for x, y in zip(alone, mixed):
         for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
             assert torch.equal(getattr(x, key), getattr(y, key)), key
+
+
+def test_matrix_core_jobs_across_launch_chunks(S):
+    """More matrix-core jobs than one launch holds (40 > 32): the second
+    chunk's partial results and bounds sit after the first's in the call's
+    workspace; every job equals the same job scored alone."""
+    rng = np.random.default_rng(41)
+    pop = S.Population.from_rows(rng.random((9000, 15)).astype(np.float32))
+    st = S.ServeState(pop, 0b11111110000, 10, 0.25)
+    reqs = [torch.from_numpy(rng.random((int(rng.integers(1, 300)), st.d)).astype(np.float32)).cuda()
+            for _ in range(40)]
+    alone = []
+    for a in reqs:
+        j = S.AlertJob.alloc(st, a, method=2)
+        S.snaps_alerts_score([j])
+        alone.append(j)
+    together = [S.AlertJob.alloc(st, a, method=2) for a in reqs]
+    S.snaps_alerts_score(together)
+    torch.cuda.synchronize()
+    for x, y in zip(alone, together):
+        for key in ("eps_count", "eps_mean", "indeg", "knn_mean", "rank"):
+            assert torch.equal(getattr(x, key), getattr(y, key)), key
