@@ -207,7 +207,7 @@ def test_object_side_passes_every_counting_object(d):
             dd = direct(q, p)
             rk = float(np.nextafter(np.float32(dd), np.float32(np.inf)))     # dd < rk, tightest
             hp = h_of(p, d)
-            for T in (0.0, f32(dd / 8), f32(dd * 0.999), rk, f32(4 * rk + 1e-3)):
+            for T in (0.0, f32(dd / 8), f32(dd * 0.999), rk, f32(4 * rk + 1e-3), 1e9):   # 1e9: clamped limit
                 L = limit(norm(q), T, d)
                 exact, loss = worst_score(q, p, L, d)
                 x = object_side_threshold(norm(q), T, rk, hp, d)
