@@ -350,6 +350,8 @@ typedef struct {
  *   ws   device workspace of snaps_alerts_workspace_bytes(jobs, n_jobs, d, k)
  *        bytes (0, and NULL allowed, when no job runs method 2); it must not
  *        be used by anything else until the call's work on stream is done.
+ *        A NULL ws that is needed, or a method outside 0..2, is SNAPS_EINVAL;
+ *        a smaller ws_bytes is SNAPS_ENOMEM; both before any device work.
  * The state header lives in device memory, so a mismatch is found on the
  * device: an alert whose state has another dimensionality than d, or a k
  * above the top-k capacity chosen for k, is not scored (eps_count and indeg
@@ -359,8 +361,9 @@ int snaps_alerts_score(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, i
                        void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace bytes snaps_alerts_score needs for these jobs: the partial
- * results of the method-2 jobs' slices; 0 for invalid arguments or when no
- * job runs method 2.  Pure host function. */
+ * results of the method-2 jobs' slices and one k-th distance bound per alert
+ * of those jobs (rounded up to 64 per job); 0 for invalid arguments or when
+ * no job runs method 2.  Pure host function. */
 size_t snaps_alerts_workspace_bytes(const snaps_alert_job* jobs, int32_t n_jobs, int32_t d, int32_t k);
 
 /* ------------------------------------------------------------------------
